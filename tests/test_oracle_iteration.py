@@ -1,0 +1,165 @@
+"""Pins of the oracle's QR, starting block, orthogonal iteration, Discretize and whole run."""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+from sklearn.metrics import adjusted_rand_score
+
+import oracle
+from paper_2408_05459_amd import synth
+
+
+def principal_sin(A, B):
+    """sin of the largest principal angle between span(A) and span(B) (Bjorck-Golub)."""
+    Qa, _ = np.linalg.qr(A)
+    Qb, _ = np.linalg.qr(B)
+    return np.linalg.norm(Qb - Qa @ (Qa.T @ Qb), 2)
+
+
+def test_qr_pos_definition():
+    rng = np.random.default_rng(0)
+    Z = rng.standard_normal((50, 7))
+    Q, R = oracle.qr_pos(Z)
+    assert np.allclose(Q @ R, Z, atol=1e-13)
+    assert np.allclose(Q.T @ Q, np.eye(7), atol=1e-14)
+    assert np.allclose(np.tril(R, -1), 0)
+    assert (np.diag(R) > 0).all()
+
+
+def test_initial_q_dependent_column_replaced():
+    n, k = 40, 4
+    labels = np.arange(n) % k
+    labels[labels == 2] = 1          # cluster 2 empty
+    C = np.concatenate([np.full((n, 1), 1 / math.sqrt(n)), oracle.normalized_bcm(labels, k)], axis=1)
+    Q = oracle.initial_q(C)
+    assert np.allclose(Q.T @ Q, np.eye(k + 1), atol=1e-13)
+    assert np.allclose(Q[:, 0], 1 / math.sqrt(n))
+    # Gram-Schmidt triangularity: column 1 lies in span{1, Yh_1}
+    assert principal_sin(C[:, :2], Q[:, :2]) < 1e-12
+    # column 3 (empty cluster 2) and column 4 (last cluster, dependent on 1) are fills
+    F = np.stack([oracle.fill_vector(n, 3), oracle.fill_vector(n, 4)], axis=1)
+    basis = np.concatenate([C[:, :3], F], axis=1)
+    assert principal_sin(basis, Q) < 1e-12
+
+
+def symmetric_case_operator(kind, seed=0):
+    """A planted network with beta = 0 and no isolated node, so P = P_N is similar to a
+    symmetric matrix (the normalised operator of the HNCut line of work)."""
+    rng = np.random.default_rng(seed)
+    n, k = 120, 3
+    labels = np.arange(n) % (k + 1)          # k+1 planted blocks: a gap after eigenvalue k+1
+    if kind == oracle.HYPERGRAPH:
+        sizes = rng.integers(2, 6, size=260)
+        ptr, idx = synth.hypergraph_incidence(labels, k + 1, sizes, 0.9, rng)
+        deg = np.bincount(idx, minlength=n)
+        assert (deg > 0).all()
+        m = sizes.shape[0]
+    else:
+        ptr, idx = synth.chung_lu_sbm(labels, k + 1, 12.0, 2.5, 0.9, rng)
+        assert (np.diff(ptr) > 0).all()
+        m = 0
+    X = rng.standard_normal((n, 3))
+    _, zero = oracle.normalize_rows(X)
+    ki, ks = oracle.knn(X, 3)
+    op = oracle.build_operator(kind, n, [ptr], [idx], m, zero, ki, ks, 0.0)
+    assert (op.beta == 0).all()
+    return op, ptr, idx, n, k, m
+
+
+@pytest.mark.parametrize("kind", [oracle.HYPERGRAPH, oracle.GRAPH])
+def test_orth_iter_converges_to_dominant_subspace(kind):
+    op, ptr, idx, n, k, m = symmetric_case_operator(kind)
+    if kind == oracle.HYPERGRAPH:
+        er = np.repeat(np.arange(m), np.diff(ptr))
+        H = np.zeros((m, n))
+        H[er, idx] = 1
+        dv = H.sum(0)
+        de = H.sum(1)
+        Theta = (H / np.sqrt(dv)[None, :]).T @ ((H / np.sqrt(dv)[None, :]) / de[:, None])
+        dsq = np.sqrt(dv)
+    else:
+        A = np.zeros((n, n))
+        rows = np.repeat(np.arange(n), np.diff(ptr))
+        A[rows, idx] = 1
+        dg = A.sum(1)
+        Theta = A / np.sqrt(np.outer(dg, dg))
+        dsq = np.sqrt(dg)
+    w, U = np.linalg.eigh(Theta)
+    order = np.argsort(-np.abs(w))
+    w = w[order]
+    assert abs(w[k + 1]) < 0.95 * abs(w[k])
+    V = U[:, order[:k + 1]] / dsq[:, None]          # eigenvectors of P_N = D^-1/2 Theta D^1/2
+    rng = np.random.default_rng(1)
+    Q0 = np.linalg.qr(rng.standard_normal((n, k + 1)))[0]
+    Q = oracle.orth_iter(op, Q0, 400)
+    assert principal_sin(V, Q) < 1e-8
+    assert np.allclose(np.abs(Q[:, 0]), 1 / math.sqrt(n), atol=1e-10)
+    # the other columns are orthogonal to the constant vector
+    assert np.abs(Q[:, 1:].sum(0)).max() < 1e-9
+
+
+def planted_rotation(n=300, k=5, noise=0.05, seed=0):
+    """Q~ = one-hot(y) R0 + noise with R0 a permuted moderate rotation.  Alg. 5 starts at
+    R = I and alternates locally, so R0 is chosen such that the first argmax is already a
+    bijection between clusters and columns."""
+    rng = np.random.default_rng(seed)
+    y = rng.integers(0, k, size=n)
+    A = rng.standard_normal((k, k)) * 0.15
+    R0 = np.eye(k)[rng.permutation(k)] @ scipy.linalg.expm(A - A.T)
+    assert len(set(np.argmax(R0, axis=1))) == k
+    Y = np.eye(k)[y]
+    Q = Y @ R0 + noise * rng.standard_normal((n, k))
+    return y, Q, R0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_discretize_recovers_planted_rotation(seed):
+    y, Q, R0 = planted_rotation(seed=seed)
+    labels, R, obj, it = oracle.discretize(Q)
+    assert adjusted_rand_score(y, labels) == 1.0
+    assert np.allclose(R.T @ R, np.eye(5), atol=1e-13)
+    # R is the orthogonal polar factor of M^T, M = Y~^T Q~ built from the returned labels
+    n, k = Q.shape
+    Qt = Q / np.linalg.norm(Q, axis=1, keepdims=True)
+    cnt = np.bincount(labels, minlength=k)
+    M = np.zeros((k, k))
+    for i in range(n):
+        M[labels[i]] += Qt[i] / cnt[labels[i]]
+    u, p = scipy.linalg.polar(M.T)
+    assert np.allclose(R, u, atol=1e-12)
+    assert abs(obj - (n - 2 * np.linalg.norm(M, "nuc"))) < 1e-9
+
+
+def test_discretize_noise_free_fixed_point():
+    y, Q, R0 = planted_rotation(noise=0.0, seed=3)
+    labels, R, obj, it = oracle.discretize(Q)
+    assert adjusted_rand_score(y, labels) == 1.0
+    assert it <= 4
+    # with exact one-hot rows the rotation is recovered up to a permutation of columns
+    P = np.abs(R0 @ R)
+    assert np.allclose(np.sort(P, axis=1)[:, -1], 1.0, atol=1e-12)
+
+
+def test_discretize_empty_cluster_completion():
+    rng = np.random.default_rng(7)
+    n, k = 60, 4
+    Q = np.zeros((n, k))
+    Q[:, 0] = 1.0
+    Q[:, 1] = rng.standard_normal(n) * 0.1
+    Q[:, 2] = rng.standard_normal(n) * 0.1
+    labels, R, obj, it = oracle.discretize(Q, max_iter=3)
+    assert np.allclose(R.T @ R, np.eye(k), atol=1e-12)
+    U = oracle.complete_null(np.eye(3)[:, :3], np.array([1.0, 0.5, 0.0]))
+    assert np.allclose(U[:, 2], [0, 0, 1])
+
+
+def test_cluster_recovers_strong_planted_partition():
+    net, prm = synth.make_config(2, scale=0.02)            # n = 2000, k = 20
+    _, zero = oracle.normalize_rows(net.X)
+    ki, ks = oracle.knn(net.X, prm.K)
+    op = oracle.build_operator(net.kind, net.n, net.ptrs, net.idxs, net.m, zero, ki, ks, prm.beta)
+    labels, rep = oracle.cluster(op, net.k, T_a=60)
+    assert adjusted_rand_score(net.labels, labels) > 0.95
+    assert rep.best_phi <= rep.phi_trace[0][1]
+    assert labels.min() >= 0 and labels.max() < net.k

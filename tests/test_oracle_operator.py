@@ -1,0 +1,235 @@
+"""Pins of the oracle's transition matrices, betas, InitBCM and MHC (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_05459_amd import synth
+
+
+def small_hypergraph(seed=0, n=30, m=20, isolated=(3,), zero_rows=(7,)):
+    rng = np.random.default_rng(seed)
+    edges = []
+    for _ in range(m):
+        s = int(rng.integers(2, 6))
+        mem = rng.choice([v for v in range(n) if v not in isolated], size=s, replace=False)
+        edges.append(sorted(int(v) for v in mem))
+    edges.append([1, 1, 2])          # repeated member: merged
+    ptr = np.zeros(len(edges) + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum([len(e) for e in edges])
+    idx = np.array([v for e in edges for v in e], dtype=np.int32)
+    X = rng.standard_normal((n, 4))
+    for z in zero_rows:
+        X[z] = 0
+    return edges, ptr, idx, X
+
+
+def walk_hypergraph(n, edges):
+    """Definition 1, topology branch: pick an incident hyperedge uniformly, then a member
+    uniformly.  Written with Python loops."""
+    sets = [sorted(set(e)) for e in edges]
+    inc = [[e for e in range(len(sets)) if v in sets[e]] for v in range(n)]
+    P = np.zeros((n, n))
+    for i in range(n):
+        for e in inc[i]:
+            for j in sets[e]:
+                P[i, j] += 1.0 / len(inc[i]) / len(sets[e])
+    return P, np.array([len(x) for x in inc])
+
+
+def walk_knn(n, nbr_idx, nbr_sim):
+    """Definition 1, KNN branch with A_K of Eq. (AK), Python loops."""
+    A = np.zeros((n, n))
+    for i in range(n):
+        for j, s in zip(nbr_idx[i], nbr_sim[i]):
+            if j < 0 or s <= 0:
+                continue
+            A[i, j] += s
+            A[j, i] += s
+    P = np.zeros((n, n))
+    for i in range(n):
+        tot = sum(A[i])
+        if tot > 0:
+            for j in range(n):
+                P[i, j] = A[i, j] / tot
+    return P, A.sum(axis=1)
+
+
+def test_hypergraph_transition_matches_walk():
+    edges, ptr, idx, X = small_hypergraph()
+    n = 30
+    Xh, zero = oracle.normalize_rows(X)
+    ki, ks = oracle.knn(X, 4)
+    op = oracle.build_operator(oracle.HYPERGRAPH, n, [ptr], [idx], len(edges), zero, ki, ks, 0.5)
+    PN_ref, delta = walk_hypergraph(n, edges)
+    PK_ref, DK = walk_knn(n, ki, ks)
+    assert np.allclose(op.P_N.toarray(), PN_ref, atol=1e-15)
+    assert np.array_equal(op.delta, delta)
+    b = np.array([0.0 if (zero[i] or DK[i] == 0) else (1.0 if delta[i] == 0 else 0.5) for i in range(n)])
+    assert np.array_equal(op.beta, b)
+    assert op.beta[3] == 1.0 and op.beta[7] == 0.0
+    P = oracle.transition_dense(op)
+    P_ref = (1 - b)[:, None] * PN_ref + b[:, None] * PK_ref
+    for i in range(n):
+        if b[i] == 0 and delta[i] == 0:
+            P_ref[i, i] = 1.0
+    assert np.allclose(P, P_ref, atol=1e-14)
+    assert np.allclose(P.sum(axis=1), 1.0, atol=1e-12)
+    assert (P >= 0).all()
+
+
+def test_graph_transition_symmetrises_and_dedupes():
+    n = 6
+    # directed input with a duplicate and a self loop
+    rows = [0, 0, 1, 2, 3, 3, 4]
+    cols = [1, 1, 2, 0, 3, 4, 5]
+    ptr = np.zeros(n + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum(np.bincount(rows, minlength=n))
+    idx = np.array(cols, dtype=np.int32)
+    top = oracle.topology_transition(oracle.GRAPH, n, [ptr], [idx])
+    A = np.zeros((n, n))
+    for r, c in zip(rows, cols):
+        if r != c:
+            A[r, c] = A[c, r] = 1
+    deg = A.sum(1)
+    ref = A / deg[:, None]
+    assert np.allclose(top["P_N"].toarray(), ref)
+    assert np.array_equal(top["delta"], deg)
+
+
+def test_multiplex_transition_average_over_active_layers():
+    n = 5
+    layers = [[(0, 1), (1, 2)], [(0, 2), (3, 4)], [(0, 1)]]
+    ptrs, idxs = [], []
+    for E in layers:
+        rows = [a for a, b in E] + [b for a, b in E]
+        cols = [b for a, b in E] + [a for a, b in E]
+        o = np.lexsort((cols, rows))
+        rows = np.array(rows)[o]
+        cols = np.array(cols)[o]
+        p = np.zeros(n + 1, dtype=np.int64)
+        p[1:] = np.cumsum(np.bincount(rows, minlength=n))
+        ptrs.append(p)
+        idxs.append(cols.astype(np.int32))
+    top = oracle.topology_transition(oracle.MULTIPLEX, n, ptrs, idxs)
+    ref = np.zeros((n, n))
+    for i in range(n):
+        act = []
+        for E in layers:
+            nb = [b for a, b in E if a == i] + [a for a, b in E if b == i]
+            if nb:
+                act.append(nb)
+        for nb in act:
+            for j in nb:
+                ref[i, j] += 1.0 / len(act) / len(nb)
+    assert np.allclose(top["P_N"].toarray(), ref)
+    assert np.allclose(top["P_N"].sum(axis=1), 1.0)
+    lit = oracle.topology_transition(oracle.MULTIPLEX, n, ptrs, idxs, literal_rw_mg=True)
+    assert np.allclose(np.asarray(lit["P_N"].sum(axis=1)).ravel()[4], 1.0 / 3.0)
+    assert top["delta"].tolist() == [3, 3, 2, 1, 1]
+
+
+@pytest.mark.parametrize("cfg", [1, 3])
+def test_generated_operators_row_stochastic(cfg):
+    net, prm = synth.make_config(cfg, scale=0.02 if cfg == 3 else 0.1)
+    Xh, zero = oracle.normalize_rows(net.X)
+    ki, ks = oracle.knn(net.X, prm.K)
+    op = oracle.build_operator(net.kind, net.n, net.ptrs, net.idxs, net.m, zero, ki, ks, prm.beta)
+    ones = np.ones((net.n, 1))
+    assert np.allclose(oracle.apply_P(op, ones), 1.0, atol=1e-12)
+    assert set(np.unique(op.beta)) <= {0.0, prm.beta, 1.0}
+
+
+def test_centres_ties_by_index():
+    delta = np.array([3, 5, 5, 1, 5, 2, 3])
+    ref = sorted(sorted(range(7), key=lambda i: (-delta[i], i))[:4])
+    assert oracle.centres(delta, 4).tolist() == ref == [0, 1, 2, 4]
+
+
+def test_init_bcm_closed_form():
+    edges, ptr, idx, X = small_hypergraph(seed=2)
+    n, k, alpha, T = 30, 3, 0.2, 7
+    _, zero = oracle.normalize_rows(X)
+    ki, ks = oracle.knn(X, 4)
+    op = oracle.build_operator(oracle.HYPERGRAPH, n, [ptr], [idx], len(edges), zero, ki, ks, 0.5)
+    labels, Pi = oracle.init_bcm(op, k, alpha, T)
+    PN, delta = walk_hypergraph(n, edges)
+    Vc = sorted(sorted(range(n), key=lambda i: (-delta[i], i))[:k])
+    Z0 = np.zeros((k, n))
+    for j, v in enumerate(Vc):
+        Z0[j, v] = 1
+    ref = np.zeros((k, n))
+    Pt = np.eye(n)
+    for t in range(T + 1):
+        ref += alpha * (1 - alpha) ** t * Z0 @ Pt
+        Pt = Pt @ PN
+    assert np.allclose(Pi, ref, atol=1e-14)
+    assert np.array_equal(labels, np.argmax(ref, axis=0))
+
+
+def test_init_bcm_two_components():
+    # two disconnected cliques; the two centres are the highest-degree nodes of each
+    n = 8
+    E = [(0, 1), (0, 2), (0, 3), (1, 2), (4, 5), (4, 6), (4, 7), (5, 6)]
+    rows = [a for a, b in E] + [b for a, b in E]
+    cols = [b for a, b in E] + [a for a, b in E]
+    o = np.lexsort((cols, rows))
+    p = np.zeros(n + 1, dtype=np.int64)
+    p[1:] = np.cumsum(np.bincount(np.array(rows)[o], minlength=n))
+    top_idx = np.array(cols)[o].astype(np.int32)
+    X = np.eye(n)
+    _, zero = oracle.normalize_rows(X)
+    ki, ks = oracle.knn(X, 2)
+    op = oracle.build_operator(oracle.GRAPH, n, [p], [top_idx], 0, zero, ki, ks, 0.5)
+    labels, _ = oracle.init_bcm(op, 2, 0.2, 25)
+    assert labels.tolist() == [0, 0, 0, 0, 1, 1, 1, 1]
+
+
+def escape_phi(S, labels, k):
+    """Eq. (mh-cond) with Python loops: mean over clusters of the escape probability."""
+    n = len(labels)
+    tot = 0.0
+    for c in range(k):
+        C = [i for i in range(n) if labels[i] == c]
+        if not C:
+            continue
+        out = 0.0
+        for i in C:
+            for j in range(n):
+                if labels[j] != c:
+                    out += S[i, j]
+        tot += out / len(C)
+    return tot / k
+
+
+@pytest.mark.parametrize("gamma", [1, 3, 5])
+def test_mhc_equals_escape_probability_plus_offset(gamma):
+    edges, ptr, idx, X = small_hypergraph(seed=4)
+    n, k, alpha = 30, 4, 0.2
+    _, zero = oracle.normalize_rows(X)
+    ki, ks = oracle.knn(X, 4)
+    op = oracle.build_operator(oracle.HYPERGRAPH, n, [ptr], [idx], len(edges), zero, ki, ks, 0.5)
+    S = oracle.multi_hop_dense(op, alpha, gamma)
+    # rows of S sum to 1 - (1-alpha)^(gamma+1)
+    assert np.allclose(S.sum(1), 1 - (1 - alpha) ** (gamma + 1), atol=1e-13)
+    rng = np.random.default_rng(gamma)
+    for _ in range(3):
+        labels = rng.integers(0, k, size=n)
+        phi = oracle.mhc(op, labels, k, alpha, gamma)
+        assert abs(phi - escape_phi(S, labels, k) - (1 - alpha) ** (gamma + 1)) < 1e-12
+
+
+def test_mhc_lemma1_upper_bound():
+    edges, ptr, idx, X = small_hypergraph(seed=5)
+    n, k, alpha, gamma = 30, 3, 0.2, 3
+    _, zero = oracle.normalize_rows(X)
+    ki, ks = oracle.knn(X, 4)
+    op = oracle.build_operator(oracle.HYPERGRAPH, n, [ptr], [idx], len(edges), zero, ki, ks, 0.5)
+    S = oracle.multi_hop_dense(op, alpha, gamma)
+    psi_sigma = np.linalg.svd(S, compute_uv=False)[:k].sum() / k
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        labels = rng.permutation(np.arange(n) % k)
+        psi = 1.0 - oracle.mhc(op, labels, k, alpha, gamma)
+        assert psi <= psi_sigma + 1e-12

@@ -1,0 +1,350 @@
+// Discretize (Sec. 7: Definition 2, Eqs. updateY and svd-in-discr, Alg. 5) on gfx950.
+//
+// Per step two kernels run:
+//  disc_pass  one thread per row: q~ = q / |q| (zero rows stay zero), t = q~ R, label = first
+//             argmax of t; the row is added to its cluster's sum S[label] and count.  The sums
+//             are kept in 2^-40 fixed point (|q~_c| <= 1) with 64-bit integer atomics, so
+//             they are exact and independent of the order in which rows arrive.
+//  disc_svd   one workgroup: M = S / count (rows of M are cluster means of q~, i.e. Y~^T Q~ with
+//             the column sums of Y as divisors), a one-sided Jacobi SVD in FP64 (Hestenes),
+//             R = V U^T, obj = n - 2 trace(Omega); sets a device flag when |obj - obj_prev| <=
+//             1e-12 max(1, |obj|).  Later steps see the flag and return at once, so labels
+//             keep the values of the last argmax, as Alg. 5 returns them.
+// Singular vectors of (numerically) zero singular values -- e.g. an empty cluster -- are
+// completed deterministically: each takes the standard basis vector with the largest
+// residual against the columns before it (smaller index on ties), orthogonalised twice.
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+constexpr double FIX_SCALE = 1099511627776.0;  // 2^40
+
+struct DiscState {
+  int done;
+  int iters;
+  double obj;
+  double obj_prev;
+};
+
+template <typename T, int KM>
+__global__ __launch_bounds__(256) void disc_pass_kernel(const T* __restrict__ Q, int64_t n, int k, int64_t ldq,
+                                                        const T* __restrict__ R, int32_t* __restrict__ labels,
+                                                        unsigned long long* __restrict__ Sg,
+                                                        unsigned int* __restrict__ cg,
+                                                        const DiscState* __restrict__ st) {
+  if (st->done) return;
+  __shared__ T Rs[KM][KM];
+  __shared__ unsigned long long Ss[KM * KM];
+  __shared__ unsigned int cs[KM];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < KM * KM; e += 256) {
+    const int i = e / KM, j = e % KM;
+    Rs[i][j] = (i < k && j < k) ? R[i * k + j] : (T)0;
+    Ss[e] = 0ull;
+  }
+  if (tid < KM) cs[tid] = 0u;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+  if (i < n) {
+    T q[KM];
+    double nr = 0.0;
+#pragma unroll
+    for (int c = 0; c < KM; c++) {
+      q[c] = (c < k) ? Q[i * ldq + c] : (T)0;
+      nr += (double)q[c] * (double)q[c];
+    }
+    if (nr > 0.0) {
+      const T inv = (T)(1.0 / sqrt(nr));
+#pragma unroll
+      for (int c = 0; c < KM; c++) q[c] *= inv;
+    }
+    int best = 0;
+    T bv = (T)0;
+#pragma unroll
+    for (int j = 0; j < KM; j++) {
+      if (j < k) {
+        T t = (T)0;
+#pragma unroll
+        for (int c = 0; c < KM; c++) t = fma(q[c], Rs[c][j], t);
+        if (j == 0 || t > bv) {
+          bv = t;
+          best = j;
+        }
+      }
+    }
+    labels[i] = best;
+    atomicAdd(&cs[best], 1u);
+#pragma unroll
+    for (int c = 0; c < KM; c++)
+      if (c < k) {
+        const long long f = llrint((double)q[c] * FIX_SCALE);
+        if (f != 0) atomicAdd(&Ss[best * KM + c], (unsigned long long)f);
+      }
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += 256) {
+    const int a = e / k, b = e % k;
+    const unsigned long long v = Ss[a * KM + b];
+    if (v != 0ull) atomicAdd(&Sg[e], v);
+  }
+  if (tid < k && cs[tid] != 0u) atomicAdd(&cg[tid], cs[tid]);
+}
+
+__device__ __forceinline__ double sgn1(double x) { return x < 0.0 ? -1.0 : 1.0; }
+
+// Columns of a k x k orthogonal factor stored as B[j][i].  Each column flagged in isnull is
+// replaced, in increasing j, by the standard basis vector with the largest residual against the
+// columns already in place (all non-null ones and the null ones completed before it), projected
+// twice and normalised.  Single thread: the rank-deficient case is rare.
+template <int KM>
+__device__ void complete_null_cols(double (*B)[KM + 1], int k, const int* isnull, int tid) {
+  if (tid != 0) return;
+  int placed[KM];
+  for (int j = 0; j < k; j++) placed[j] = !isnull[j];
+  for (int j = 0; j < k; j++) {
+    if (!isnull[j]) continue;
+    int bi = 0;
+    double bn = -1.0;
+    for (int i = 0; i < k; i++) {
+      double n2 = 0.0;
+      for (int a = 0; a < k; a++) {
+        double w = (a == i) ? 1.0 : 0.0;
+        for (int c = 0; c < k; c++)
+          if (placed[c]) w -= B[c][a] * B[c][i];
+        n2 += w * w;
+      }
+      if (n2 > bn) {
+        bn = n2;
+        bi = i;
+      }
+    }
+    double w[KM];
+    for (int a = 0; a < k; a++) w[a] = (a == bi) ? 1.0 : 0.0;
+    for (int pass = 0; pass < 2; pass++)
+      for (int c = 0; c < k; c++) {
+        if (!placed[c]) continue;
+        double dp = 0.0;
+        for (int a = 0; a < k; a++) dp += B[c][a] * w[a];
+        for (int a = 0; a < k; a++) w[a] -= dp * B[c][a];
+      }
+    double nn = 0.0;
+    for (int a = 0; a < k; a++) nn += w[a] * w[a];
+    nn = sqrt(nn);
+    for (int a = 0; a < k; a++) B[j][a] = w[a] / nn;
+    placed[j] = 1;
+  }
+}
+
+template <typename T, int KM>
+__global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __restrict__ Sg, unsigned int* __restrict__ cg,
+                                                       int k, int64_t n, double* __restrict__ Rd, T* __restrict__ Rt,
+                                                       DiscState* __restrict__ st) {
+  if (st->done) return;
+  __shared__ double A[KM][KM + 1];   // A[j][i] = column j of M (then of M V)
+  __shared__ double V[KM][KM + 1];   // V[j][i] = column j of V
+  __shared__ double sig[KM];
+  __shared__ int isnull[KM];
+  __shared__ int s_rot;
+  const int tid = threadIdx.x;
+  // M[c][j] = S[c][j] 2^-40 / count[c]; then clear S and counts for the next step
+  for (int e = tid; e < KM * KM; e += 256) {
+    const int c = e / KM, j = e % KM;
+    double v = 0.0;
+    if (c < k && j < k) {
+      const unsigned int cnt = cg[c];
+      const long long s = (long long)Sg[c * k + j];
+      v = cnt ? ((double)s / FIX_SCALE) / (double)cnt : 0.0;
+    }
+    A[j][c] = v;
+    V[j][c] = (c == j && c < k) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += 256) Sg[e] = 0ull;
+  if (tid < k) cg[tid] = 0u;
+
+  // one-sided Jacobi on the columns of A (round-robin pairs; k padded to even with a zero column)
+  const int kk = k + (k & 1);
+  const int npairs = kk / 2;
+  const int tpp = 256 / 32;  // 8 threads per pair (npairs <= 32)
+  const int pair = tid / tpp, sub = tid % tpp;
+  for (int sweep = 0; sweep < 40; sweep++) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int step = 0; step < kk - 1; step++) {
+      if (pair < npairs) {
+        const int m = pair;
+        auto pos = [&](int x) { return x == 0 ? 0 : ((x - 1 + step) % (kk - 1)) + 1; };
+        int p = pos(m), q = pos(kk - 1 - m);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        double al = 0.0, be = 0.0, ga = 0.0;
+        if (q < k) {
+          for (int i = sub; i < k; i += tpp) {
+            const double x = A[p][i], y = A[q][i];
+            al += x * x;
+            be += y * y;
+            ga += x * y;
+          }
+        }
+        // reduce over the 8 lanes of the pair (consecutive lanes of one wave)
+        for (int o = tpp / 2; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o, tpp);
+          be += __shfl_xor(be, o, tpp);
+          ga += __shfl_xor(ga, o, tpp);
+        }
+        if (q < k && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = sgn1(zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t);
+          const double s = c * t;
+          for (int i = sub; i < k; i += tpp) {
+            const double x = A[p][i], y = A[q][i];
+            A[p][i] = c * x - s * y;
+            A[q][i] = s * x + c * y;
+            const double vx = V[p][i], vy = V[q][i];
+            V[p][i] = c * vx - s * vy;
+            V[q][i] = s * vx + c * vy;
+          }
+          if (sub == 0) s_rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (s_rot == 0) break;
+    __syncthreads();
+  }
+  // singular values sigma_j = |a_j|; left vectors u_j = a_j / sigma_j in place.  R = sum_j v_j u_j^T
+  // does not depend on the order of the pairs, so no sort is needed.
+  if (tid < k) {
+    double s2 = 0.0;
+    for (int i = 0; i < k; i++) s2 += A[tid][i] * A[tid][i];
+    sig[tid] = sqrt(s2);
+  }
+  __syncthreads();
+  double smax = 0.0, ssum = 0.0;
+  for (int i = 0; i < k; i++) {
+    smax = fmax(smax, sig[i]);
+    ssum += sig[i];
+  }
+  int nnull = 0;
+  if (tid < k) {
+    const bool nz = smax > 0.0 && sig[tid] > 1e-12 * smax;
+    isnull[tid] = nz ? 0 : 1;
+    for (int i = 0; i < k; i++) A[tid][i] = nz ? A[tid][i] / sig[tid] : 0.0;
+  }
+  __syncthreads();
+  for (int i = 0; i < k; i++) nnull += isnull[i];
+  if (nnull > 0) {
+    complete_null_cols<KM>(A, k, isnull, tid);
+    complete_null_cols<KM>(V, k, isnull, tid);
+  }
+  __syncthreads();
+  // R = V U^T
+  for (int e = tid; e < k * k; e += 256) {
+    const int a = e / k, b = e % k;
+    double s = 0.0;
+    for (int j = 0; j < k; j++) s += V[j][a] * A[j][b];
+    Rd[e] = s;
+    Rt[e] = (T)s;
+  }
+  if (tid == 0) {
+    const double obj = (double)n - 2.0 * ssum;
+    st->iters += 1;
+    if (st->iters > 1 && fabs(obj - st->obj) <= 1e-12 * fmax(1.0, fabs(obj))) st->done = 1;
+    st->obj_prev = st->obj;
+    st->obj = obj;
+  }
+}
+
+template <typename T>
+__global__ void disc_init_kernel(int k, double* __restrict__ Rd, T* __restrict__ Rt, DiscState* __restrict__ st,
+                                 unsigned long long* __restrict__ Sg, unsigned int* __restrict__ cg) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < k * k) {
+    const double v = (e / k == e % k) ? 1.0 : 0.0;
+    Rd[e] = v;
+    Rt[e] = (T)v;
+    Sg[e] = 0ull;
+  }
+  if (e < k) cg[e] = 0u;
+  if (e == 0) {
+    st->done = 0;
+    st->iters = 0;
+    st->obj = 0.0;
+    st->obj_prev = 0.0;
+  }
+}
+
+template <typename T, int KM>
+ancka_status disc_launch(ancka_ctx* ctx, const T* Q, int64_t n, int k, int64_t ldq, int max_iter, int32_t* labels,
+                         double* Rh, double* obj, int32_t* iters) {
+  double* Rd = nullptr;
+  T* Rt = nullptr;
+  unsigned long long* Sg = nullptr;
+  unsigned int* cg = nullptr;
+  DiscState* st = nullptr;
+  ST_TRY(ws_get_t(ctx, "disc_Rd", 64 * 64, &Rd));
+  ST_TRY(ws_get_t(ctx, "disc_Rt", 64 * 64, &Rt));
+  ST_TRY(ws_get_t(ctx, "disc_S", 64 * 64, &Sg));
+  ST_TRY(ws_get_t(ctx, "disc_c", 64, &cg));
+  ST_TRY(ws_get_t(ctx, "disc_st", 1, &st));
+  disc_init_kernel<T><<<16, 256, 0, ctx->stream>>>(k, Rd, Rt, st, Sg, cg);
+  LAUNCH_CHECK(ctx);
+  const unsigned grid = (unsigned)cdiv(n, 256);
+  DiscState hs{0, 0, 0.0, 0.0};
+  for (int it = 0; it < max_iter; it++) {
+    disc_pass_kernel<T, KM><<<grid, 256, 0, ctx->stream>>>(Q, n, k, ldq, Rt, labels, Sg, cg, st);
+    LAUNCH_CHECK(ctx);
+    disc_svd_kernel<T, KM><<<1, 256, 0, ctx->stream>>>(Sg, cg, k, n, Rd, Rt, st);
+    LAUNCH_CHECK(ctx);
+    if ((it % 4) == 3 || it == max_iter - 1) {
+      HIP_TRY(ctx, hipMemcpyAsync(&hs, st, sizeof(DiscState), hipMemcpyDeviceToHost, ctx->stream));
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      if (hs.done) break;
+    }
+  }
+  if (Rh) {
+    std::vector<double> h(k * k);
+    HIP_TRY(ctx, hipMemcpyAsync(h.data(), Rd, sizeof(double) * k * k, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int e = 0; e < k * k; e++) Rh[e] = h[e];
+  }
+  if (obj) *obj = hs.obj;
+  if (iters) *iters = hs.iters;
+  return ANCKA_OK;
+}
+
+template <typename T>
+ancka_status disc_typed(ancka_ctx* ctx, const T* Q, int64_t n, int k, int64_t ldq, int max_iter, int32_t* labels,
+                        double* Rh, double* obj, int32_t* iters) {
+  if (k <= 8) return disc_launch<T, 8>(ctx, Q, n, k, ldq, max_iter, labels, Rh, obj, iters);
+  if (k <= 16) return disc_launch<T, 16>(ctx, Q, n, k, ldq, max_iter, labels, Rh, obj, iters);
+  if (k <= 32) return disc_launch<T, 32>(ctx, Q, n, k, ldq, max_iter, labels, Rh, obj, iters);
+  return disc_launch<T, 64>(ctx, Q, n, k, ldq, max_iter, labels, Rh, obj, iters);
+}
+
+}  // namespace
+
+ancka_status discretize_internal(ancka_ctx* ctx, const void* Q, int qdtype, int64_t n, int k, int64_t ldq,
+                                 int max_iter, int32_t* labels, double* R, double* obj, int32_t* iters) {
+  if (qdtype == ANCKA_F64)
+    return disc_typed<double>(ctx, (const double*)Q, n, k, ldq, max_iter, labels, R, obj, iters);
+  return disc_typed<float>(ctx, (const float*)Q, n, k, ldq, max_iter, labels, R, obj, iters);
+}
+
+extern "C" ancka_status ancka_discretize(ancka_ctx* ctx, const void* Q, int32_t qdtype, int64_t n, int32_t k,
+                                         int64_t ldq, int32_t max_iter, int32_t* labels, double* R, double* obj,
+                                         int32_t* iters) {
+  if (!ctx || !Q || !labels) return ANCKA_ERR_INVALID_ARG;
+  if (k < 1 || k > 64 || n < 1 || ldq < k || max_iter < 1 || (qdtype != ANCKA_F32 && qdtype != ANCKA_F64))
+    return set_err(ctx, ANCKA_ERR_INVALID_ARG, "ancka_discretize: n=%lld k=%d ldq=%lld max_iter=%d", (long long)n, k,
+                   (long long)ldq, max_iter);
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, ANCKA_ERR_HIP, "hipSetDevice");
+  return discretize_internal(ctx, Q, qdtype, n, k, ldq, max_iter, labels, R, obj, iters);
+}

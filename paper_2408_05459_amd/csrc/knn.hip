@@ -1,0 +1,685 @@
+// K nearest neighbours by cosine similarity (Sec. 3.1; Alg. 6 lines 1-5) on gfx950.
+//
+// Modes
+//  EXACT_F64     FP64 tiles; the top-K list is final (similarity = dot / sqrt(|x_i|^2 |x_j|^2)).
+//  EXACT_F32     FP32 tiles -> top-2K candidates -> FP64 rescoring -> top-K + certificate.
+//  BF16_RESCORE  BF16 MFMA tiles (FP32 accumulation of exact products) -> as EXACT_F32.
+//
+// Certificate: a candidate outside the 2K list has an approximate score no larger than the
+// 2K-th listed one, a; its exact score is at most a + eps, eps bounding the tile arithmetic
+// (fp32 accumulation: gamma_d = d u / (1 - d u) plus the roundings of the inverse norms, with a
+// safety factor 4).  When the K-th rescored similarity exceeds a + eps no outside candidate can
+// enter the top K, otherwise the row is recomputed exactly over all n candidates.
+#include <cfloat>
+#include <climits>
+#include <cmath>
+
+#include "common.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t v) { return __uint_as_float(((uint32_t)v) << 16); }
+
+template <typename TX>
+__device__ __forceinline__ double load_as_double(const TX* p, int64_t i);
+template <>
+__device__ __forceinline__ double load_as_double<double>(const double* p, int64_t i) { return p[i]; }
+template <>
+__device__ __forceinline__ double load_as_double<float>(const float* p, int64_t i) { return (double)p[i]; }
+template <>
+__device__ __forceinline__ double load_as_double<uint16_t>(const uint16_t* p, int64_t i) {
+  return (double)bf16_to_f32(p[i]);
+}
+
+// key order: larger similarity first, then smaller index
+template <typename T>
+__device__ __forceinline__ bool better(T s, int j, T s2, int j2) {
+  return s > s2 || (s == s2 && j < j2);
+}
+
+// ---- prologue: |x_i|^2 in FP64, 1/|x_i|, |x_i|, optional zero-padded bf16 copy -----------
+template <typename TX>
+__global__ __launch_bounds__(256) void knn_prologue_kernel(const TX* __restrict__ X, int64_t n, int64_t d, int64_t ldx,
+                                                           double* __restrict__ sq, float* __restrict__ invn,
+                                                           float* __restrict__ nrm, uint16_t* __restrict__ Xp, int DP,
+                                                           unsigned long long* __restrict__ zero_count) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / ANCKA_WAVE;
+  const int lane = threadIdx.x % ANCKA_WAVE;
+  if (row >= n) return;
+  const TX* xr = X + row * ldx;
+  double acc = 0.0;
+  for (int64_t c = lane; c < d; c += ANCKA_WAVE) {
+    const double v = load_as_double<TX>(xr, c);
+    acc += v * v;
+  }
+  acc = wave_sum(acc);
+  if (Xp) {
+    uint16_t* xp = Xp + row * (int64_t)DP;
+    for (int c = lane; c < DP; c += ANCKA_WAVE) {
+      uint16_t v = 0;
+      if (c < d) v = ((const uint16_t*)(const void*)xr)[c];
+      xp[c] = v;
+    }
+  }
+  if (lane == 0) {
+    sq[row] = acc;
+    const double nr = sqrt(acc);
+    invn[row] = acc > 0.0 ? (float)(1.0 / nr) : 0.0f;
+    nrm[row] = (float)nr;
+    if (acc == 0.0) atomicAdd(zero_count, 1ull);
+  }
+}
+
+// per tile of `tile` candidate rows: the smallest norm of a non-zero row (+inf if none)
+__global__ void tile_min_norm_kernel(const float* __restrict__ nrm, int64_t n, int tile, float* __restrict__ out,
+                                     int64_t ntiles) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  float m = INFINITY;
+  for (int64_t j = t * tile; j < n && j < (t + 1) * tile; j++) {
+    const float v = nrm[j];
+    if (v > 0.0f && v < m) m = v;
+  }
+  out[t] = m;
+}
+
+// ---- exact tiles with vector FMA (EXACT_F64 / EXACT_F32) -----------------------------------
+// 64 queries x 64 candidates per step, 4x4 outputs per thread, d streamed in chunks of 16.
+// The score tile goes to LDS; thread r < 64 owns query r's list of length KP (sorted).
+constexpr int VT_Q = 64;
+constexpr int VT_C = 64;
+constexpr int VT_D = 16;
+
+template <typename T, typename TX>
+__global__ __launch_bounds__(256) void knn_vector_kernel(const TX* __restrict__ X, int64_t n, int64_t d, int64_t ldx,
+                                                         const double* __restrict__ sq, const float* __restrict__ invn,
+                                                         int KP, int exact_div, int32_t* __restrict__ cand_idx,
+                                                         T* __restrict__ cand_sim) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* As = (T*)smem;                       // [VT_D][VT_Q]
+  T* Bs = As + VT_D * VT_Q;               // [VT_D][VT_C]
+  T* S = Bs + VT_D * VT_C;                // [VT_Q][VT_C + 1]
+  T* lsim = S + VT_Q * (VT_C + 1);        // [VT_Q][KP]
+  int* lidx = (int*)(lsim + VT_Q * KP);   // [VT_Q][KP]
+
+  const int tid = threadIdx.x;
+  const int ty = tid / 16, tx = tid % 16;
+  const int64_t q0 = (int64_t)blockIdx.x * VT_Q;
+
+  for (int e = tid; e < VT_Q * KP; e += 256) {
+    lsim[e] = -INFINITY;
+    lidx[e] = INT_MAX;
+  }
+  // query owner state
+  const int64_t my_q = q0 + tid;
+  const bool owner = tid < VT_Q && my_q < n;
+  T my_sq = 0, my_inv = 0;
+  if (owner) {
+    my_sq = (T)sq[my_q];
+    my_inv = (T)invn[my_q];
+  }
+  const bool my_zero = owner && sq[my_q] == 0.0;
+  __syncthreads();
+
+  const int64_t ntiles = cdiv(n, VT_C);
+  for (int64_t t = 0; t < ntiles; t++) {
+    const int64_t c0 = t * VT_C;
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) acc[i][j] = 0;
+    for (int64_t k0 = 0; k0 < d; k0 += VT_D) {
+      // thread loads 4 elements of one row of each tile: row = tid / 4, cols (tid % 4) * 4 ..
+      const int lr = tid / 4, lc = (tid % 4) * 4;
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int64_t kk = k0 + lc + u;
+        const int64_t qr = q0 + lr, cr = c0 + lr;
+        As[(lc + u) * VT_Q + lr] = (qr < n && kk < d) ? (T)load_as_double<TX>(X, qr * ldx + kk) : (T)0;
+        Bs[(lc + u) * VT_C + lr] = (cr < n && kk < d) ? (T)load_as_double<TX>(X, cr * ldx + kk) : (T)0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < VT_D; kk++) {
+        T a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) a[i] = As[kk * VT_Q + ty * 4 + i];
+#pragma unroll
+        for (int j = 0; j < 4; j++) b[j] = Bs[kk * VT_C + tx * 4 + j];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+          for (int j = 0; j < 4; j++) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) S[(ty * 4 + i) * (VT_C + 1) + tx * 4 + j] = acc[i][j];
+    __syncthreads();
+    if (owner && !my_zero) {
+      T* ls = lsim + tid * KP;
+      int* li = lidx + tid * KP;
+      T thr = ls[KP - 1];
+      int thr_i = li[KP - 1];
+      for (int c = 0; c < VT_C; c++) {
+        const int64_t j = c0 + c;
+        if (j >= n || j == my_q) continue;
+        const double sqj = sq[j];
+        if (sqj == 0.0) continue;
+        const T dot = S[tid * (VT_C + 1) + c];
+        T s;
+        if (exact_div) s = dot / sqrt(my_sq * (T)sqj);
+        else s = dot * (my_inv * (T)invn[j]);
+        const int jj = (int)j;
+        if (!better<T>(s, jj, thr, thr_i)) continue;
+        int p = KP - 1;
+        while (p > 0 && better<T>(s, jj, ls[p - 1], li[p - 1])) {
+          ls[p] = ls[p - 1];
+          li[p] = li[p - 1];
+          p--;
+        }
+        ls[p] = s;
+        li[p] = jj;
+        thr = ls[KP - 1];
+        thr_i = li[KP - 1];
+      }
+    }
+    __syncthreads();
+  }
+  if (owner) {
+    for (int r = 0; r < KP; r++) {
+      const int j = lidx[tid * KP + r];
+      cand_idx[my_q * KP + r] = (j == INT_MAX) ? -1 : j;
+      cand_sim[my_q * KP + r] = (j == INT_MAX) ? (T)0 : lsim[tid * KP + r];
+    }
+  }
+}
+
+// ---- BF16 MFMA tiles ------------------------------------------------------------------------
+// Workgroup = 4 waves; wave w owns QW queries (QW/32 column blocks of the 32x32 MFMA output),
+// held in registers as B operands for the whole kernel.  Candidate tiles of 64 rows (two 32-row
+// A blocks) stream through double-buffered LDS.  Epilogue: a lane holds 16 candidates of one
+// query per (A block, B block); their maximum is compared with the query's threshold scaled by
+// the tile's smallest norm (a necessary condition), and only then are candidates scored exactly
+// (dot * 1/|x_j|) and inserted into the query's sorted list in LDS.
+constexpr int BT_C = 64;   // candidates per tile
+
+template <int DP, int QW>
+__global__ __launch_bounds__(256, 1) void knn_bf16_kernel(const uint16_t* __restrict__ Xp, int64_t n,
+                                                          const float* __restrict__ invn,
+                                                          const float* __restrict__ tile_min, int KP,
+                                                          int32_t* __restrict__ cand_idx, float* __restrict__ cand_sim) {
+  constexpr int KS = DP / 16;           // MFMA k-steps
+  constexpr int NQB = QW / 32;          // query blocks per wave
+  constexpr int QB = 4 * QW;            // queries per workgroup
+  constexpr int LDR = DP + 8;           // LDS row stride in bf16 (16-byte pad)
+  constexpr int CHUNKS = BT_C * DP / 8; // 16-byte chunks per tile
+  constexpr int CPT = CHUNKS / 256;     // chunks per thread
+  static_assert(CHUNKS % 256 == 0, "tile chunks");
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint16_t* tileb = (uint16_t*)smem;                         // [2][BT_C][LDR]
+  float* tinv = (float*)(tileb + 2 * BT_C * LDR);            // [2][BT_C]
+  float* lsim = tinv + 2 * BT_C;                             // [QB][KP]
+  int* lidx = (int*)(lsim + QB * KP);                        // [QB][KP]
+
+  const int tid = threadIdx.x;
+  const int wave = tid / ANCKA_WAVE;
+  const int lane = tid % ANCKA_WAVE;
+  const int l32 = lane % 32;
+  const int half = lane / 32;
+  const int64_t q0 = (int64_t)blockIdx.x * QB;
+
+  for (int e = tid; e < QB * KP; e += 256) {
+    lsim[e] = -INFINITY;
+    lidx[e] = INT_MAX;
+  }
+
+  // query fragments: lane holds 8 bf16 of query row (l32) at k = ks*16 + half*8
+  bf16x8 bq[NQB][KS];
+  float thr[NQB];
+  int qloc[NQB];
+  int64_t qglob[NQB];
+#pragma unroll
+  for (int qb = 0; qb < NQB; qb++) {
+    qloc[qb] = wave * QW + qb * 32 + l32;
+    qglob[qb] = q0 + qloc[qb];
+    const bool valid = qglob[qb] < n && invn[qglob[qb] < n ? qglob[qb] : 0] > 0.0f;
+    thr[qb] = valid ? -INFINITY : INFINITY;
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++) {
+      if (qglob[qb] < n) {
+        const uint4 v = *(const uint4*)(Xp + qglob[qb] * DP + ks * 16 + half * 8);
+        bq[qb][ks] = __builtin_bit_cast(bf16x8, v);
+      } else {
+        bq[qb][ks] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+      }
+    }
+  }
+
+  const int64_t ntiles = cdiv(n, BT_C);
+  uint4 pre[CPT];
+  float pre_inv = 0.0f;
+  auto prefetch = [&](int64_t t) {
+#pragma unroll
+    for (int u = 0; u < CPT; u++) {
+      const int c = u * 256 + tid;
+      const int r = c / (DP / 8), c8 = c % (DP / 8);
+      const int64_t j = t * BT_C + r;
+      pre[u] = (j < n) ? *(const uint4*)(Xp + j * DP + c8 * 8) : make_uint4(0, 0, 0, 0);
+    }
+    if (tid < BT_C) {
+      const int64_t j = t * BT_C + tid;
+      pre_inv = (j < n) ? invn[j] : 0.0f;
+    }
+  };
+  auto commit = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < CPT; u++) {
+      const int c = u * 256 + tid;
+      const int r = c / (DP / 8), c8 = c % (DP / 8);
+      *(uint4*)(tileb + (buf * BT_C + r) * LDR + c8 * 8) = pre[u];
+    }
+    if (tid < BT_C) tinv[buf * BT_C + tid] = pre_inv;
+  };
+
+  prefetch(0);
+  commit(0);
+  __syncthreads();
+
+  for (int64_t t = 0; t < ntiles; t++) {
+    const int buf = (int)(t & 1);
+    if (t + 1 < ntiles) prefetch(t + 1);
+
+    f32x16 acc[2][NQB];
+#pragma unroll
+    for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+      for (int qb = 0; qb < NQB; qb++)
+#pragma unroll
+        for (int i = 0; i < 16; i++) acc[cb][qb][i] = 0.0f;
+
+    const uint16_t* tb = tileb + buf * BT_C * LDR;
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++) {
+      bf16x8 a[2];
+#pragma unroll
+      for (int cb = 0; cb < 2; cb++) {
+        const uint4 v = *(const uint4*)(tb + (cb * 32 + l32) * LDR + ks * 16 + half * 8);
+        a[cb] = __builtin_bit_cast(bf16x8, v);
+      }
+#pragma unroll
+      for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+        for (int qb = 0; qb < NQB; qb++)
+          acc[cb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[cb], bq[qb][ks], acc[cb][qb], 0, 0, 0);
+    }
+
+    // ---- epilogue: filter, then exact insertion for the rare hits
+    const float mn = tile_min[t];
+#pragma unroll
+    for (int qb = 0; qb < NQB; qb++) {
+      float m = -INFINITY;
+#pragma unroll
+      for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+        for (int i = 0; i < 16; i++) m = fmaxf(m, acc[cb][qb][i]);
+      const float th = thr[qb];
+      const float fth = (th >= 0.0f) ? th * mn * (1.0f - 1e-6f) : (th == INFINITY ? INFINITY : -INFINITY);
+      const bool hit = m >= fth;
+      if (__ballot(hit)) {
+        const int q = qloc[qb];
+        const int64_t qi = qglob[qb];
+        float* ls = lsim + q * KP;
+        int* li = lidx + q * KP;
+        for (int h = 0; h < 2; h++) {
+          if (hit && half == h) {
+            float tcur = ls[KP - 1];
+            int tcur_i = li[KP - 1];
+#pragma unroll
+            for (int cb = 0; cb < 2; cb++) {
+#pragma unroll
+              for (int i = 0; i < 16; i++) {
+                const int cl = cb * 32 + 8 * (i / 4) + 4 * half + (i % 4);
+                const int64_t j = t * BT_C + cl;
+                const float iv = tinv[buf * BT_C + cl];
+                const float s = acc[cb][qb][i] * iv;
+                const int jj = (int)j;
+                if (iv > 0.0f && j != qi && better<float>(s, jj, tcur, tcur_i)) {
+                  int p = KP - 1;
+                  while (p > 0 && better<float>(s, jj, ls[p - 1], li[p - 1])) {
+                    ls[p] = ls[p - 1];
+                    li[p] = li[p - 1];
+                    p--;
+                  }
+                  ls[p] = s;
+                  li[p] = jj;
+                  tcur = ls[KP - 1];
+                  tcur_i = li[KP - 1];
+                }
+              }
+            }
+          }
+          __threadfence_block();
+        }
+        if (thr[qb] != INFINITY) thr[qb] = ls[KP - 1];
+      }
+    }
+
+    if (t + 1 < ntiles) commit(buf ^ 1);
+    __syncthreads();
+  }
+
+  // write the lists (scores scaled by 1/|x_i| to cosine)
+#pragma unroll
+  for (int qb = 0; qb < NQB; qb++) {
+    const int64_t qi = qglob[qb];
+    if (qi >= n || half != 0) continue;
+    const float iq = invn[qi];
+    const int q = qloc[qb];
+    for (int r = 0; r < KP; r++) {
+      const int j = lidx[q * KP + r];
+      cand_idx[qi * KP + r] = (j == INT_MAX) ? -1 : j;
+      cand_sim[qi * KP + r] = (j == INT_MAX) ? 0.0f : lsim[q * KP + r] * iq;
+    }
+  }
+}
+
+// ---- FP64 rescoring of the candidate lists + certificate --------------------------------------
+// One wave per row.  s_ij = dot / sqrt(|x_i|^2 |x_j|^2) with the dot accumulated in FP64 by
+// lanes over d and reduced by a butterfly (identical for (i,j) and (j,i)).
+template <typename TX>
+__device__ __forceinline__ double exact_dot(const TX* __restrict__ X, int64_t ldx, int64_t d, int64_t i, int64_t j,
+                                            int lane) {
+  double acc = 0.0;
+  const TX* xi = X + i * ldx;
+  const TX* xj = X + j * ldx;
+  for (int64_t c = lane; c < d; c += ANCKA_WAVE) acc += load_as_double<TX>(xi, c) * load_as_double<TX>(xj, c);
+  return wave_sum(acc);
+}
+
+// bitonic sort of 64 (s, j) pairs across a wave, best first
+__device__ __forceinline__ void wave_sort_desc(double& s, int& j, int lane) {
+  for (int k = 2; k <= 64; k <<= 1) {
+    for (int st = k >> 1; st > 0; st >>= 1) {
+      const double so = __shfl_xor(s, st, 64);
+      const int jo = __shfl_xor(j, st, 64);
+      const bool up = ((lane & k) == 0);          // this block sorted best-first
+      const bool lower = ((lane & st) == 0);
+      const bool mine_better = better<double>(s, j, so, jo);
+      // lower element of the pair should hold the better one in an "up" block
+      const bool keep = (lower == up) ? mine_better : !mine_better;
+      if (!keep) {
+        s = so;
+        j = jo;
+      }
+    }
+  }
+}
+
+template <typename TX>
+__global__ __launch_bounds__(256) void knn_rescore_kernel(const TX* __restrict__ X, int64_t n, int64_t d, int64_t ldx,
+                                                          const double* __restrict__ sq, int KP, int K,
+                                                          const int32_t* __restrict__ cand_idx,
+                                                          const float* __restrict__ cand_sim, double eps,
+                                                          int32_t* __restrict__ nbr_idx, float* __restrict__ nbr_sim,
+                                                          int32_t* __restrict__ uncert_rows,
+                                                          unsigned int* __restrict__ uncert_count) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / ANCKA_WAVE;
+  const int lane = threadIdx.x % ANCKA_WAVE;
+  if (i >= n) return;
+  double my_s = -INFINITY;
+  int my_j = INT_MAX;
+  int valid = 0;
+  const double sqi = sq[i];
+  for (int r = 0; r < KP; r++) {
+    const int j = cand_idx[i * KP + r];
+    if (j < 0) continue;
+    valid++;
+    const double dot = exact_dot<TX>(X, ldx, d, i, j, lane);
+    const double s = dot / sqrt(sqi * sq[j]);
+    if (lane == r) {
+      my_s = s;
+      my_j = j;
+    }
+  }
+  wave_sort_desc(my_s, my_j, lane);
+  if (lane < K) {
+    const bool ok = my_j != INT_MAX;
+    nbr_idx[i * K + lane] = ok ? my_j : -1;
+    nbr_sim[i * K + lane] = ok ? (float)my_s : 0.0f;
+  }
+  // certificate (only when the list was full: otherwise it holds every candidate)
+  const double sK = __shfl(my_s, K - 1, 64);
+  if (lane == 0 && valid == KP) {
+    const double a = (double)cand_sim[i * KP + KP - 1];
+    if (!(sK > a + eps)) {
+      const unsigned int slot = atomicAdd(uncert_count, 1u);
+      uncert_rows[slot] = (int32_t)i;
+    }
+  }
+}
+
+// ---- exact recompute of uncertified rows: one workgroup per row, every candidate ------------
+template <typename TX>
+__global__ __launch_bounds__(256) void knn_exact_rows_kernel(const TX* __restrict__ X, int64_t n, int64_t d,
+                                                             int64_t ldx, const double* __restrict__ sq, int K,
+                                                             const int32_t* __restrict__ rows,
+                                                             int32_t* __restrict__ nbr_idx, float* __restrict__ nbr_sim) {
+  __shared__ double ls[4][64];
+  __shared__ int li[4][64];
+  const int wave = threadIdx.x / ANCKA_WAVE;
+  const int lane = threadIdx.x % ANCKA_WAVE;
+  const int64_t i = rows[blockIdx.x];
+  const double sqi = sq[i];
+  // wave-private list in lanes: (s, j) sorted best-first across lanes 0..K-1
+  double s_l = -INFINITY;
+  int j_l = INT_MAX;
+  double thr = -INFINITY;
+  int thr_i = INT_MAX;
+  for (int64_t j = wave; j < n; j += 4) {
+    if (j == i) continue;
+    const double sqj = sq[j];
+    if (sqj == 0.0) continue;
+    const double dot = exact_dot<TX>(X, ldx, d, i, j, lane);
+    const double s = dot / sqrt(sqi * sqj);
+    if (better<double>(s, (int)j, thr, thr_i)) {
+      // insert: lanes with a worse element shift down by one
+      const bool worse = !better<double>(s_l, j_l, s, (int)j);
+      const double s_up = __shfl_up(s_l, 1, 64);
+      const int j_up = __shfl_up(j_l, 1, 64);
+      const bool worse_up = lane > 0 && !better<double>(s_up, j_up, s, (int)j);
+      if (worse) {
+        if (worse_up) {
+          s_l = s_up;
+          j_l = j_up;
+        } else {
+          s_l = s;
+          j_l = (int)j;
+        }
+      }
+      thr = __shfl(s_l, K - 1, 64);
+      thr_i = __shfl(j_l, K - 1, 64);
+    }
+  }
+  ls[wave][lane] = (lane < K) ? s_l : -INFINITY;
+  li[wave][lane] = (lane < K) ? j_l : INT_MAX;
+  __syncthreads();
+  if (wave == 0) {
+    // merge 4 lists of K (K <= 16 per list fits 64 lanes) -> sort -> top K
+    double s = -INFINITY;
+    int j = INT_MAX;
+    const int w = lane / 16, r = lane % 16;
+    if (r < K) {
+      s = ls[w][r];
+      j = li[w][r];
+    }
+    wave_sort_desc(s, j, lane);
+    if (lane < K) {
+      nbr_idx[i * K + lane] = (j == INT_MAX) ? -1 : j;
+      nbr_sim[i * K + lane] = (j == INT_MAX) ? 0.0f : (float)s;
+    }
+  }
+}
+
+template <typename TX>
+ancka_status run_vector(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_t ldx, const double* sq,
+                        const float* invn, int KP, bool f64, int32_t* cidx, void* csim) {
+  const unsigned grid = (unsigned)cdiv(n, VT_Q);
+  static bool attr_set = false;
+  if (!attr_set) {
+    HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_vector_kernel<double, TX>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_vector_kernel<float, TX>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr_set = true;
+  }
+  if (f64) {
+    const size_t sm = sizeof(double) * (2 * VT_D * VT_Q + VT_Q * (VT_C + 1) + VT_Q * KP) + sizeof(int) * VT_Q * KP;
+    knn_vector_kernel<double, TX><<<grid, 256, sm, ctx->stream>>>(X, n, d, ldx, sq, invn, KP, 1, cidx, (double*)csim);
+  } else {
+    const size_t sm = sizeof(float) * (2 * VT_D * VT_Q + VT_Q * (VT_C + 1) + VT_Q * KP) + sizeof(int) * VT_Q * KP;
+    knn_vector_kernel<float, TX><<<grid, 256, sm, ctx->stream>>>(X, n, d, ldx, sq, invn, KP, 0, cidx, (float*)csim);
+  }
+  LAUNCH_CHECK(ctx);
+  return ANCKA_OK;
+}
+
+template <int DP, int QW>
+ancka_status run_bf16_t(ancka_ctx* ctx, const uint16_t* Xp, int64_t n, const float* invn, const float* tmin, int KP,
+                        int32_t* cidx, float* csim) {
+  constexpr int QB = 4 * QW;
+  const size_t sm = (size_t)2 * BT_C * (DP + 8) * 2 + 2 * BT_C * 4 + (size_t)QB * KP * 8;
+  static bool attr_set = false;
+  if (!attr_set) {
+    HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_bf16_kernel<DP, QW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     160 * 1024));
+    attr_set = true;
+  }
+  if (sm > 160 * 1024) return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "knn: LDS budget exceeded (d=%d, K'=%d)", DP, KP);
+  knn_bf16_kernel<DP, QW><<<(unsigned)cdiv(n, QB), 256, sm, ctx->stream>>>(Xp, n, invn, tmin, KP, cidx, csim);
+  LAUNCH_CHECK(ctx);
+  return ANCKA_OK;
+}
+
+ancka_status run_bf16(ancka_ctx* ctx, int DP, const uint16_t* Xp, int64_t n, const float* invn, const float* tmin,
+                      int KP, int32_t* cidx, float* csim) {
+  switch (DP) {
+    case 32: return run_bf16_t<32, 64>(ctx, Xp, n, invn, tmin, KP, cidx, csim);
+    case 64: return run_bf16_t<64, 64>(ctx, Xp, n, invn, tmin, KP, cidx, csim);
+    case 128: return run_bf16_t<128, 64>(ctx, Xp, n, invn, tmin, KP, cidx, csim);
+    case 256: return run_bf16_t<256, 64>(ctx, Xp, n, invn, tmin, KP, cidx, csim);
+    case 512: return run_bf16_t<512, 32>(ctx, Xp, n, invn, tmin, KP, cidx, csim);
+    default: return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "knn: bf16 path supports d <= 512 (got padded %d)", DP);
+  }
+}
+
+template <typename TX>
+ancka_status rescore_and_fix(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_t ldx, const double* sq, int KP,
+                             int K, const int32_t* cidx, const float* csim, int32_t* nbr_idx, float* nbr_sim,
+                             ancka_knn_stats* st) {
+  int32_t* urows = nullptr;
+  unsigned int* ucount = nullptr;
+  ST_TRY(ws_get_t(ctx, "knn_urows", (size_t)n, &urows));
+  ST_TRY(ws_get_t(ctx, "knn_ucount", 4, &ucount));
+  ST_TRY(fill_zero(ctx, ucount, 4 * sizeof(unsigned int)));
+  const double u = ldexp(1.0, -24);
+  const double gd = (double)d * u / (1.0 - (double)d * u);
+  const double eps = 4.0 * (gd + 4.0 * u);
+  knn_rescore_kernel<TX><<<(unsigned)cdiv(n, 4), 256, 0, ctx->stream>>>(X, n, d, ldx, sq, KP, K, cidx, csim, eps,
+                                                                        nbr_idx, nbr_sim, urows, ucount);
+  LAUNCH_CHECK(ctx);
+  unsigned int hcount = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&hcount, ucount, sizeof(unsigned int), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (hcount > 0) {
+    knn_exact_rows_kernel<TX><<<hcount, 256, 0, ctx->stream>>>(X, n, d, ldx, sq, K, urows, nbr_idx, nbr_sim);
+    LAUNCH_CHECK(ctx);
+  }
+  if (st) {
+    st->uncertified_rows = hcount;
+    st->recomputed_rows = hcount;
+  }
+  return ANCKA_OK;
+}
+
+template <typename TX>
+ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_t ldx, int K, int mode,
+                       int32_t* nbr_idx, void* nbr_sim, ancka_knn_stats* st) {
+  double* sq = nullptr;
+  float *invn = nullptr, *nrm = nullptr;
+  unsigned long long* zc = nullptr;
+  ST_TRY(ws_get_t(ctx, "knn_sq", (size_t)n, &sq));
+  ST_TRY(ws_get_t(ctx, "knn_invn", (size_t)n, &invn));
+  ST_TRY(ws_get_t(ctx, "knn_nrm", (size_t)n, &nrm));
+  ST_TRY(ws_get_t(ctx, "knn_zero", 2, &zc));
+  ST_TRY(fill_zero(ctx, zc, 16));
+  uint16_t* Xp = nullptr;
+  int DP = 0;
+  if (mode == ANCKA_KNN_BF16_RESCORE) {
+    DP = 32;
+    while (DP < d) DP *= 2;
+    if (DP > 512) return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "knn: bf16 path supports d <= 512");
+    ST_TRY(ws_get_t(ctx, "knn_xp", (size_t)n * DP, &Xp));
+  }
+  knn_prologue_kernel<TX><<<(unsigned)cdiv(n, 4), 256, 0, ctx->stream>>>(X, n, d, ldx, sq, invn, nrm, Xp, DP, zc);
+  LAUNCH_CHECK(ctx);
+
+  if (mode == ANCKA_KNN_EXACT_F64) {
+    int KP = K;
+    ST_TRY(run_vector<TX>(ctx, X, n, d, ldx, sq, invn, KP, true, nbr_idx, nbr_sim));
+    if (st) st->uncertified_rows = st->recomputed_rows = 0;
+  } else {
+    const int KP = 2 * K;
+    int32_t* cidx = nullptr;
+    float* csim = nullptr;
+    ST_TRY(ws_get_t(ctx, "knn_cidx", (size_t)n * KP, &cidx));
+    ST_TRY(ws_get_t(ctx, "knn_csim", (size_t)n * KP, &csim));
+    if (mode == ANCKA_KNN_EXACT_F32) {
+      ST_TRY(run_vector<TX>(ctx, X, n, d, ldx, sq, invn, KP, false, cidx, csim));
+    } else {
+      const int64_t nt = cdiv(n, BT_C);
+      float* tmin = nullptr;
+      ST_TRY(ws_get_t(ctx, "knn_tmin", (size_t)nt, &tmin));
+      tile_min_norm_kernel<<<(unsigned)cdiv(nt, 256), 256, 0, ctx->stream>>>(nrm, n, BT_C, tmin, nt);
+      LAUNCH_CHECK(ctx);
+      ST_TRY(run_bf16(ctx, DP, Xp, n, invn, tmin, KP, cidx, csim));
+    }
+    ST_TRY(rescore_and_fix<TX>(ctx, X, n, d, ldx, sq, KP, K, cidx, csim, nbr_idx, (float*)nbr_sim, st));
+  }
+  if (st) {
+    unsigned long long hz = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&hz, zc, sizeof(hz), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    st->zero_rows = (int64_t)hz;
+  }
+  return ANCKA_OK;
+}
+
+}  // namespace
+
+extern "C" ancka_status ancka_knn(ancka_ctx* ctx, const void* X, int32_t xdtype, int64_t n, int64_t d, int64_t ldx,
+                                  int32_t K, int32_t mode, int32_t* nbr_idx, void* nbr_sim, ancka_knn_stats* stats) {
+  if (!ctx) return ANCKA_ERR_INVALID_ARG;
+  if (!X || !nbr_idx || !nbr_sim || n < 2 || d < 1 || ldx < d || K < 1 || K > n - 1 || n > INT32_MAX - 64 ||
+      K > (mode == ANCKA_KNN_EXACT_F64 ? 64 : 16))
+    return set_err(ctx, ANCKA_ERR_INVALID_ARG, "ancka_knn: invalid arguments (n=%lld d=%lld ldx=%lld K=%d)",
+                   (long long)n, (long long)d, (long long)ldx, K);
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, ANCKA_ERR_HIP, "hipSetDevice");
+  if (mode == ANCKA_KNN_BF16_RESCORE && xdtype != ANCKA_BF16)
+    return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "ancka_knn: BF16_RESCORE needs bf16 attributes");
+  if (mode < 0 || mode > 2) return set_err(ctx, ANCKA_ERR_INVALID_ARG, "ancka_knn: unknown mode %d", mode);
+  if (stats) *stats = ancka_knn_stats{0, 0, 0};
+  switch (xdtype) {
+    case ANCKA_F64: return knn_typed<double>(ctx, (const double*)X, n, d, ldx, K, mode, nbr_idx, nbr_sim, stats);
+    case ANCKA_F32: return knn_typed<float>(ctx, (const float*)X, n, d, ldx, K, mode, nbr_idx, nbr_sim, stats);
+    case ANCKA_BF16: return knn_typed<uint16_t>(ctx, (const uint16_t*)X, n, d, ldx, K, mode, nbr_idx, nbr_sim, stats);
+    default: return set_err(ctx, ANCKA_ERR_INVALID_ARG, "ancka_knn: unknown dtype %d", xdtype);
+  }
+}

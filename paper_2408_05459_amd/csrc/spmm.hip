@@ -1,0 +1,392 @@
+// Sparse products with the walk operator (Eqs. zt, mhc-comp-ancka, pi_c_t) on gfx950.
+//
+// One kernel covers every product the method needs.  For output row r:
+//   acc = sum_seg tscale[seg] * sum_{p in seg} tcol[idx[p]*segs + l] * tsrc[idx[p]]     (topology)
+//       + sum_{p in knn row r} kval[p] * ksrc[kidx[p]]                                   (KNN walk)
+//       + self[r] * ssrc[r]                                                              (self term)
+//   out[r] = a * acc + epilogue(r)
+// A row is owned by LPR lanes; each lane owns VW consecutive columns and loads them with one
+// 16-byte access per gathered row, so a gather of row j is one coalesced 16*LPR-byte request.
+// Neighbour indices are read cooperatively (one per lane) and broadcast inside the lane group.
+// Sums run in CSR order, so results are deterministic.
+#include "common.h"
+
+namespace {
+
+template <typename T>
+struct V16;
+template <>
+struct V16<float> {
+  typedef float4 type;
+  static constexpr int W = 4;
+};
+template <>
+struct V16<double> {
+  typedef double2 type;
+  static constexpr int W = 2;
+};
+
+template <typename T>
+__device__ __forceinline__ void vload(const T* p, T (&v)[V16<T>::W]) {
+  const typename V16<T>::type x = *(const typename V16<T>::type*)p;
+  if constexpr (V16<T>::W == 4) {
+    v[0] = x.x;
+    v[1] = x.y;
+    v[2] = x.z;
+    v[3] = x.w;
+  } else {
+    v[0] = x.x;
+    v[1] = x.y;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void vstore(T* p, const T (&v)[V16<T>::W]) {
+  typename V16<T>::type x;
+  if constexpr (V16<T>::W == 4) {
+    x.x = v[0];
+    x.y = v[1];
+    x.z = v[2];
+    x.w = v[3];
+  } else {
+    x.x = v[0];
+    x.y = v[1];
+  }
+  *(typename V16<T>::type*)p = x;
+}
+
+enum { EPI_NONE = 0, EPI_MHC = 1, EPI_INIT = 2 };
+
+template <typename T>
+struct SpmmArgs {
+  int64_t rows;
+  int segs;
+  const int64_t* tptr;
+  const int32_t* tidx;
+  const T* tscale;   // per segment, nullable (= 1)
+  const T* tcol;     // per (source row, layer), nullable (= 1)
+  const T* tsrc;
+  int64_t tld;       // leading dimension of tsrc
+  const int64_t* kptr;  // nullable: no KNN part
+  const int32_t* kidx;
+  const T* kval;
+  const T* ksrc;
+  const T* self;     // nullable
+  T selfu;           // uniform self coefficient when self == nullptr
+  const T* ssrc;     // nullable: no self term
+  T* out;
+  int64_t ld;        // leading dimension of out, ksrc and ssrc
+  int cols;
+  T a;
+  int epi;
+  const int32_t* labels;   // EPI_MHC: label of each row; EPI_INIT: centre index of each row or -1
+  const int32_t* counts;   // EPI_MHC: cluster sizes
+  T b;
+};
+
+template <typename T, int LPR>
+__device__ __forceinline__ void gather_segment(const int64_t beg, const int64_t end, const int32_t* __restrict__ idx,
+                                               const T* __restrict__ colw, int colw_stride, int colw_off,
+                                               const T* __restrict__ vals, const T* __restrict__ src, int64_t ld,
+                                               int sub, bool col_ok, int coff, T (&acc)[V16<T>::W]) {
+  constexpr int W = V16<T>::W;
+  for (int64_t p0 = beg; p0 < end; p0 += LPR) {
+    const int64_t myp = p0 + sub;
+    int32_t jm = 0;
+    T wm = (T)0;
+    if (myp < end) {
+      jm = idx[myp];
+      wm = vals ? vals[myp] : (T)1;
+      if (colw) wm *= colw[(int64_t)jm * colw_stride + colw_off];
+    }
+    const int cnt = (int)((end - p0) < LPR ? (end - p0) : LPR);
+    int u = 0;
+    for (; u + 4 <= cnt; u += 4) {
+      int32_t j[4];
+      T w[4];
+      T v[4][W];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        j[q] = __shfl(jm, u + q, LPR);
+        w[q] = __shfl(wm, u + q, LPR);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        if (col_ok) vload<T>(src + (int64_t)j[q] * ld + coff, v[q]);
+        else {
+#pragma unroll
+          for (int c = 0; c < W; c++) v[q][c] = (T)0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+#pragma unroll
+        for (int c = 0; c < W; c++) acc[c] = fma(w[q], v[q][c], acc[c]);
+    }
+    for (; u < cnt; u++) {
+      const int32_t j = __shfl(jm, u, LPR);
+      const T w = __shfl(wm, u, LPR);
+      T v[W];
+      if (col_ok) {
+        vload<T>(src + (int64_t)j * ld + coff, v);
+#pragma unroll
+        for (int c = 0; c < W; c++) acc[c] = fma(w, v[c], acc[c]);
+      }
+    }
+  }
+}
+
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void spmm_kernel(const SpmmArgs<T> A) {
+  constexpr int W = V16<T>::W;
+  constexpr int RPB = 256 / LPR;
+  const int sub = threadIdx.x % LPR;
+  const int64_t r = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR;
+  if (r >= A.rows) return;   // whole lane groups exit together
+  const int coff = sub * W;
+  const bool col_ok = coff < A.cols;
+  T acc[W];
+#pragma unroll
+  for (int c = 0; c < W; c++) acc[c] = (T)0;
+
+  for (int l = 0; l < A.segs; l++) {
+    const int64_t seg = r * A.segs + l;
+    const int64_t b = A.tptr[seg], e = A.tptr[seg + 1];
+    if (b == e) continue;
+    T part[W];
+#pragma unroll
+    for (int c = 0; c < W; c++) part[c] = (T)0;
+    gather_segment<T, LPR>(b, e, A.tidx, A.tcol, A.segs, l, nullptr, A.tsrc, A.tld, sub, col_ok, coff, part);
+    const T s = A.tscale ? A.tscale[seg] : (T)1;
+#pragma unroll
+    for (int c = 0; c < W; c++) acc[c] = fma(s, part[c], acc[c]);
+  }
+  if (A.kptr) {
+    gather_segment<T, LPR>(A.kptr[r], A.kptr[r + 1], A.kidx, nullptr, 0, 0, A.kval, A.ksrc, A.ld, sub, col_ok, coff,
+                           acc);
+  }
+  if (A.ssrc && col_ok) {
+    const T sc = A.self ? A.self[r] : A.selfu;
+    if (sc != (T)0) {
+      T v[W];
+      vload<T>(A.ssrc + r * A.ld + coff, v);
+#pragma unroll
+      for (int c = 0; c < W; c++) acc[c] = fma(sc, v[c], acc[c]);
+    }
+  }
+  if (!col_ok) return;
+  T o[W];
+#pragma unroll
+  for (int c = 0; c < W; c++) o[c] = A.a * acc[c];
+  if (A.epi == EPI_MHC) {
+    const int lab = A.labels[r];
+    const int c = lab - coff;
+    if (c >= 0 && c < W) o[c] += A.b / sqrt((T)A.counts[lab]);
+  } else if (A.epi == EPI_INIT) {
+    const int cj = A.labels[r];
+    const int c = cj - coff;
+    if (cj >= 0 && c >= 0 && c < W) o[c] += A.b;
+  }
+  vstore<T>(A.out + r * A.ld + coff, o);
+}
+
+template <typename T>
+ancka_status launch_spmm(ancka_ctx* ctx, SpmmArgs<T> A) {
+  if (A.rows <= 0) return ANCKA_OK;
+  constexpr int W = V16<T>::W;
+  const int need = (A.cols + W - 1) / W;
+  int lpr = 2;
+  while (lpr < need) lpr *= 2;
+  if (lpr > 64) return set_err(ctx, ANCKA_ERR_INVALID_ARG, "spmm: %d columns exceed one wave", A.cols);
+  const unsigned grid = (unsigned)cdiv(A.rows, 256 / lpr);
+  switch (lpr) {
+    case 2: spmm_kernel<T, 2><<<grid, 256, 0, ctx->stream>>>(A); break;
+    case 4: spmm_kernel<T, 4><<<grid, 256, 0, ctx->stream>>>(A); break;
+    case 8: spmm_kernel<T, 8><<<grid, 256, 0, ctx->stream>>>(A); break;
+    case 16: spmm_kernel<T, 16><<<grid, 256, 0, ctx->stream>>>(A); break;
+    case 32: spmm_kernel<T, 32><<<grid, 256, 0, ctx->stream>>>(A); break;
+    default: spmm_kernel<T, 64><<<grid, 256, 0, ctx->stream>>>(A); break;
+  }
+  LAUNCH_CHECK(ctx);
+  return ANCKA_OK;
+}
+
+template <typename T>
+SpmmArgs<T> blank(int64_t rows, T* out, int64_t ld, int cols) {
+  SpmmArgs<T> A;
+  A.rows = rows;
+  A.segs = 1;
+  A.tptr = nullptr;
+  A.tidx = nullptr;
+  A.tscale = nullptr;
+  A.tcol = nullptr;
+  A.tsrc = nullptr;
+  A.tld = ld;
+  A.kptr = nullptr;
+  A.kidx = nullptr;
+  A.kval = nullptr;
+  A.ksrc = nullptr;
+  A.self = nullptr;
+  A.selfu = (T)0;
+  A.ssrc = nullptr;
+  A.out = out;
+  A.ld = ld;
+  A.cols = cols;
+  A.a = (T)1;
+  A.epi = EPI_NONE;
+  A.labels = nullptr;
+  A.counts = nullptr;
+  A.b = (T)0;
+  return A;
+}
+
+// P Q with optional epilogue (EPI_NONE: plain; EPI_MHC: (1-alpha) P F + alpha Yh)
+template <typename T>
+ancka_status apply_typed(ancka_ctx* ctx, const ancka_op* op, const T* Q, T* Z, int cols, int64_t ld, T a, int epi,
+                         const int32_t* labels, const int32_t* counts, T b) {
+  const int64_t n = op->n;
+  const T* topo_src = Q;
+  if (op->kind == ANCKA_HYPERGRAPH) {
+    T* E = nullptr;
+    ST_TRY(ws_get_t(ctx, "spmm_E", (size_t)op->m * ld, &E));
+    SpmmArgs<T> S1 = blank<T>(op->m, E, ld, cols);
+    S1.tptr = op->eptr;
+    S1.tidx = op->eidx;
+    S1.tscale = (const T*)op->escale;
+    S1.tsrc = Q;
+    ST_TRY(launch_spmm<T>(ctx, S1));
+    topo_src = E;
+  }
+  SpmmArgs<T> S = blank<T>(n, Z, ld, cols);
+  S.segs = op->kind == ANCKA_HYPERGRAPH ? 1 : op->L;
+  S.tptr = op->tptr;
+  S.tidx = op->tidx;
+  S.tscale = (const T*)op->tscale;
+  S.tsrc = topo_src;
+  S.kptr = op->kptr;
+  S.kidx = op->kidx;
+  S.kval = (const T*)op->kval;
+  S.ksrc = Q;
+  S.self = (const T*)op->self;
+  S.ssrc = Q;
+  S.a = a;
+  S.epi = epi;
+  S.labels = labels;
+  S.counts = counts;
+  S.b = b;
+  return launch_spmm<T>(ctx, S);
+}
+
+template <typename T>
+ancka_status init_typed(ancka_ctx* ctx, const ancka_op* op, const T* Pin, T* Pout, int cols, int64_t ld, T a,
+                        const int32_t* centre_of, T b) {
+  const int64_t n = op->n;
+  if (op->kind == ANCKA_HYPERGRAPH) {
+    T* E = nullptr;
+    ST_TRY(ws_get_t(ctx, "spmm_E", (size_t)op->m * ld, &E));
+    SpmmArgs<T> S1 = blank<T>(op->m, E, ld, cols);
+    S1.tptr = op->eptr;
+    S1.tidx = op->eidx;
+    S1.tscale = (const T*)op->escale;
+    S1.tcol = (const T*)op->tcol;   // 1/delta(v) of the source node
+    S1.tsrc = Pin;
+    ST_TRY(launch_spmm<T>(ctx, S1));
+    SpmmArgs<T> S2 = blank<T>(n, Pout, ld, cols);
+    S2.tptr = op->tptr;
+    S2.tidx = op->tidx;
+    S2.tsrc = E;
+    S2.a = a;
+    S2.epi = EPI_INIT;
+    S2.labels = centre_of;
+    S2.b = b;
+    return launch_spmm<T>(ctx, S2);
+  }
+  SpmmArgs<T> S = blank<T>(n, Pout, ld, cols);
+  S.segs = op->L;
+  S.tptr = op->tptr;
+  S.tidx = op->tidx;
+  S.tcol = (const T*)op->tcol;      // 1/(L_j deg_l(j)) of the source node in layer l
+  S.tsrc = Pin;
+  S.a = a;
+  S.epi = EPI_INIT;
+  S.labels = centre_of;
+  S.b = b;
+  return launch_spmm<T>(ctx, S);
+}
+
+}  // namespace
+
+ancka_status op_apply(ancka_ctx* ctx, const ancka_op* op, const void* Q, void* Z, int cols, int64_t ld) {
+  if (op->dtype == ANCKA_F64)
+    return apply_typed<double>(ctx, op, (const double*)Q, (double*)Z, cols, ld, 1.0, EPI_NONE, nullptr, nullptr, 0.0);
+  return apply_typed<float>(ctx, op, (const float*)Q, (float*)Z, cols, ld, 1.0f, EPI_NONE, nullptr, nullptr, 0.0f);
+}
+
+ancka_status op_apply_mhc(ancka_ctx* ctx, const ancka_op* op, const void* Q, void* Z, int cols, int64_t ld,
+                          double alpha, const int32_t* labels, const int32_t* counts) {
+  if (op->dtype == ANCKA_F64)
+    return apply_typed<double>(ctx, op, (const double*)Q, (double*)Z, cols, ld, 1.0 - alpha, EPI_MHC, labels, counts,
+                               alpha);
+  return apply_typed<float>(ctx, op, (const float*)Q, (float*)Z, cols, ld, (float)(1.0 - alpha), EPI_MHC, labels,
+                            counts, (float)alpha);
+}
+
+ancka_status op_apply_init(ancka_ctx* ctx, const ancka_op* op, const void* Pin, void* Pout, int cols, int64_t ld,
+                           double alpha, const int32_t* centre_of) {
+  if (op->dtype == ANCKA_F64)
+    return init_typed<double>(ctx, op, (const double*)Pin, (double*)Pout, cols, ld, 1.0 - alpha, centre_of, alpha);
+  return init_typed<float>(ctx, op, (const float*)Pin, (float*)Pout, cols, ld, (float)(1.0 - alpha), centre_of,
+                           (float)alpha);
+}
+
+ancka_status op_apply_features(ancka_ctx* ctx, const ancka_op* op, const float* Xh, float* U, int cols, int64_t ld) {
+  // U = 0.5 Xh + 0.5 P_N Xh, column panels of at most 64
+  for (int c0 = 0; c0 < cols; c0 += 64) {
+    const int w = (cols - c0) < 64 ? (cols - c0) : 64;
+    const float* src = Xh + c0;
+    float* dst = U + c0;
+    if (op->kind == ANCKA_HYPERGRAPH) {
+      float* E = nullptr;
+      ST_TRY(ws_get_t(ctx, "spmm_Ef", (size_t)op->m * 64, &E));
+      SpmmArgs<float> S1 = blank<float>(op->m, E, 64, w);
+      S1.tptr = op->eptr;
+      S1.tidx = op->eidx;
+      S1.tscale = (const float*)op->escale;
+      S1.tsrc = src;
+      S1.tld = ld;
+      ST_TRY(launch_spmm<float>(ctx, S1));
+      SpmmArgs<float> S2 = blank<float>(op->n, dst, ld, w);
+      S2.tptr = op->tptr;
+      S2.tidx = op->tidx;
+      S2.tscale = (const float*)op->tcol;   // 1/delta(u) per node
+      S2.tsrc = E;
+      S2.tld = 64;
+      S2.ssrc = src;
+      S2.selfu = 1.0f;
+      S2.a = 0.5f;
+      ST_TRY(launch_spmm<float>(ctx, S2));
+    } else {
+      SpmmArgs<float> S = blank<float>(op->n, dst, ld, w);
+      S.segs = op->L;
+      S.tptr = op->tptr;
+      S.tidx = op->tidx;
+      S.tscale = (const float*)op->tcol;    // 1/(L_i deg_l(i)) per segment
+      S.tsrc = src;
+      S.ssrc = src;
+      S.selfu = 1.0f;
+      S.a = 0.5f;
+      ST_TRY(launch_spmm<float>(ctx, S));
+    }
+  }
+  return ANCKA_OK;
+}
+
+extern "C" ancka_status ancka_apply_p(ancka_ctx* ctx, const ancka_op* op, const void* Q, void* Z, int32_t cols,
+                                      int64_t ld) {
+  if (!ctx || !op || !Q || !Z) return ANCKA_ERR_INVALID_ARG;
+  const int vw = op->dtype == ANCKA_F64 ? 2 : 4;
+  if (cols < 1 || cols > 64 || ld < cols || ld % vw != 0)
+    return set_err(ctx, ANCKA_ERR_INVALID_ARG, "ancka_apply_p: cols=%d ld=%lld (ld must be a multiple of %d)", cols,
+                   (long long)ld, vw);
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, ANCKA_ERR_HIP, "hipSetDevice");
+  return op_apply(ctx, op, Q, Z, cols, ld);
+}

@@ -1,0 +1,247 @@
+"""GPU parity: every step of the HIP path (through the C ABI) against the FP64 oracle.
+
+Inputs are seeded parity-sized variants of the five workloads (same distributions, smaller
+n; several tiles plus a ragged tail).  Tolerances:
+  KNN          tie-aware sets with tol = 2 gamma_d (u = 2^-24 for the FP32/BF16 modes, whose
+               final similarities are FP64-rescored; u = 2^-53 for the FP64 mode);
+  P Q, MHC     FP32: |err| <= 1e-5 |ref|max (gather sums of <= a few hundred terms in FP32);
+               FP64: 1e-12;
+  QR blocks    max |Q_gpu - Q_oracle| <= 1e-5 (FP32) / 1e-11 (FP64) for the unique QR;
+  iterations   sin(largest principal angle) <= 1e-4 (the target's subspace tolerance);
+  whole run    ARI(gpu, oracle) >= 0.99 and |phi_gpu - phi_oracle| <= 1e-4 phi_oracle, phi_gpu
+               evaluated by the oracle's MHC on the GPU labels.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_05459_amd import synth
+from tests.helpers import ari, check_knn_rows, gamma_d, oracle_operator, principal_sin
+
+pytestmark = pytest.mark.gpu
+
+SCALES = {1: 0.5, 2: 0.03, 3: 0.006, 4: 0.002}
+_CACHE = {}
+
+
+def workload(cfg):
+    if cfg not in _CACHE:
+        net, prm = synth.make_config(cfg, scale=SCALES[cfg])
+        op, ki, ks = oracle_operator(net, prm.K, prm.beta)
+        _CACHE[cfg] = (net, prm, op, ki, ks)
+    return _CACHE[cfg]
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+def tol_knn(prm, d):
+    return 2 * gamma_d(d, 2.0 ** -53 if prm.knn_mode == "f64" else 2.0 ** -24)
+
+
+def gpu_op_from_oracle_knn(lib, net, prm, ki, ks):
+    torch = torch_mod()
+    s, keep = lib.network(net)
+    idx = torch.from_numpy(ki.astype(np.int32)).cuda()
+    sim = torch.from_numpy(ks.astype(np.float64 if prm.q_dtype == "f64" else np.float32)).cuda()
+    op = lib.build_operator(s, idx, sim, prm.K, prm.beta, prm.q_dtype)
+    return op, (s, keep)
+
+
+def qdt(prm):
+    torch = torch_mod()
+    return torch.float64 if prm.q_dtype == "f64" else torch.float32
+
+
+def rtol_of(prm):
+    return 1e-12 if prm.q_dtype == "f64" else 1e-5
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
+def test_knn_parity(lib, cfg):
+    net, prm, op, ki, ks = workload(cfg)
+    torch = torch_mod()
+    from paper_2408_05459_amd.binding import upload_attributes
+    X = upload_attributes(net.X, net.x_dtype)
+    idx, sim, st = lib.knn(X, prm.K, prm.knn_mode)
+    torch.cuda.synchronize()
+    gi = idx.cpu().numpy()
+    gs = sim.cpu().numpy()
+    rows = np.arange(net.n)
+    swaps = check_knn_rows(net.X, rows, gi, gs, prm.K, tol_knn(prm, net.d))
+    print(f"cfg {cfg}: n={net.n} tie swaps={swaps} uncertified={st.uncertified_rows}")
+    assert swaps <= max(1, net.n // 1000) or prm.knn_mode == "f64"
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
+def test_operator_parity(lib, cfg):
+    net, prm, op, ki, ks = workload(cfg)
+    torch = torch_mod()
+    gop, keep = gpu_op_from_oracle_knn(lib, net, prm, ki, ks)
+    info = gop.info()
+    assert np.array_equal(info["delta"], op.delta.astype(np.int64))
+    assert np.array_equal(info["beta"], op.beta)
+    DK = np.asarray(op.P_K.sum(axis=1)).ravel()   # P_K rows sum to 1 or 0
+    dk_ref = np.asarray(oracle.knn_adjacency(net.n, ki, ks).sum(axis=1)).ravel()
+    assert np.allclose(info["dk"], dk_ref, rtol=1e-6 if prm.q_dtype == "f32" else 1e-13, atol=0)
+    assert info["nnz_knn"] == oracle.knn_adjacency(net.n, ki, ks).nnz
+    rng = np.random.default_rng(cfg)
+    kp = net.k + 1
+    ld = kp + (-kp) % (2 if prm.q_dtype == "f64" else 4)
+    Qh = np.zeros((net.n, ld))
+    Qh[:, :kp] = rng.standard_normal((net.n, kp))
+    Q = torch.from_numpy(Qh).to(qdt(prm)).cuda()
+    Z = gop.apply(Q)
+    Zg = Z.cpu().double().numpy()[:, :kp]
+    Zr = oracle.apply_P(op, Q.cpu().double().numpy()[:, :kp])
+    err = np.abs(Zg - Zr).max() / np.abs(Zr).max()
+    assert err <= rtol_of(prm) * 10, err
+    # row-stochastic: P 1 = 1
+    ones = torch.ones((net.n, ld), dtype=qdt(prm), device="cuda")
+    P1 = gop.apply(ones).cpu().double().numpy()[:, :kp]
+    assert np.abs(P1 - 1.0).max() <= (1e-12 if prm.q_dtype == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
+def test_init_bcm_parity(lib, cfg):
+    net, prm, op, ki, ks = workload(cfg)
+    gop, keep = gpu_op_from_oracle_knn(lib, net, prm, ki, ks)
+    g = gop.init_bcm(net.k, prm.alpha, prm.T_i).cpu().numpy()
+    r, Pi = oracle.init_bcm(op, net.k, prm.alpha, prm.T_i)
+    diff = np.nonzero(g != r)[0]
+    if prm.q_dtype == "f64":
+        assert diff.size == 0
+    else:
+        # a disagreement is only allowed where the oracle's two best scores nearly tie
+        for j in diff:
+            col = np.sort(Pi[:, j])
+            assert col[-1] - col[-2] <= 1e-5 * max(col[-1], 1e-30), (j, col[-2:])
+        assert diff.size <= max(1, net.n // 1000)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
+def test_mhc_parity(lib, cfg):
+    net, prm, op, ki, ks = workload(cfg)
+    torch = torch_mod()
+    gop, keep = gpu_op_from_oracle_knn(lib, net, prm, ki, ks)
+    rng = np.random.default_rng(7)
+    for labels in [net.labels, rng.integers(0, net.k, size=net.n)]:
+        lt = torch.from_numpy(labels.astype(np.int32)).cuda()
+        phi_g = gop.mhc(lt, net.k, prm.alpha, prm.gamma)
+        phi_r = oracle.mhc(op, labels, net.k, prm.alpha, prm.gamma)
+        assert abs(phi_g - phi_r) <= rtol_of(prm) * abs(phi_r), (phi_g, phi_r)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
+def test_initial_block_and_orth_iter_parity(lib, cfg):
+    net, prm, op, ki, ks = workload(cfg)
+    torch = torch_mod()
+    gop, keep = gpu_op_from_oracle_knn(lib, net, prm, ki, ks)
+    y0, _ = oracle.init_bcm(op, net.k, prm.alpha, prm.T_i)
+    C = np.concatenate([np.full((net.n, 1), 1 / math.sqrt(net.n)), oracle.normalized_bcm(y0, net.k)], axis=1)
+    Q0r = oracle.initial_q(C)
+    lt = torch.from_numpy(y0.astype(np.int32)).cuda()
+    Q = gop.initial_block(net.k, labels=lt)
+    kp = net.k + 1
+    Q0g = Q.cpu().double().numpy()[:, :kp]
+    assert np.abs(Q0g - Q0r).max() <= (1e-11 if prm.q_dtype == "f64" else 1e-5)
+    G = Q0g.T @ Q0g
+    assert np.abs(G - np.eye(kp)).max() <= (1e-12 if prm.q_dtype == "f64" else 1e-5)
+    Qr = Q0r
+    done = 0
+    for t in [1, 5, 50]:
+        R, dq = gop.orth_iter(Q, kp, t - done)
+        Qr = oracle.orth_iter(op, Qr, t - done)
+        done = t
+        Qg = Q.cpu().double().numpy()[:, :kp]
+        s = principal_sin(Qr, Qg)
+        orth = np.abs(Qg.T @ Qg - np.eye(kp)).max()
+        print(f"cfg {cfg} t={t}: sin={s:.2e} orth={orth:.2e} dq={dq:.3e}")
+        assert s <= 1e-4
+        assert orth <= (1e-12 if prm.q_dtype == "f64" else 1e-5)
+        assert np.allclose(np.diag(R), np.abs(np.diag(R)))
+    # per-column agreement of the unique QR iterates (signs fixed by diag(R) > 0)
+    assert np.abs(Qg[:, 0] - Qr[:, 0]).max() <= 1e-4
+
+
+def planted_rotation(n=3000, k=7, noise=0.05, seed=0):
+    import scipy.linalg
+    rng = np.random.default_rng(seed)
+    y = rng.integers(0, k, size=n)
+    A = rng.standard_normal((k, k)) * 0.15
+    R0 = np.eye(k)[rng.permutation(k)] @ scipy.linalg.expm(A - A.T)
+    Q = np.eye(k)[y] @ R0 + noise * rng.standard_normal((n, k))
+    return y, Q
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_discretize_parity_planted(lib, dtype):
+    torch = torch_mod()
+    y, Qh = planted_rotation()
+    k = Qh.shape[1]
+    lr, Rr, objr, itr = oracle.discretize(Qh)
+    # block stored with one leading column (the dropped constant eigenvector) and padding
+    ld = 8
+    full = np.zeros((Qh.shape[0], ld))
+    full[:, 1:k + 1] = Qh
+    T = torch.from_numpy(full).to(torch.float64 if dtype == "f64" else torch.float32).cuda()
+    lg, Rg, objg, itg = lib.discretize(T[:, 1:], k)
+    lg = lg.cpu().numpy()
+    assert ari(y, lg) == 1.0
+    assert np.array_equal(lg, lr)
+    assert np.abs(Rg - Rr).max() <= (1e-10 if dtype == "f64" else 1e-5)
+    assert abs(objg - objr) <= (1e-8 if dtype == "f64" else 1e-3)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 4])
+def test_discretize_parity_iterated_block(lib, cfg):
+    net, prm, op, ki, ks = workload(cfg)
+    torch = torch_mod()
+    y0, _ = oracle.init_bcm(op, net.k, prm.alpha, prm.T_i)
+    C = np.concatenate([np.full((net.n, 1), 1 / math.sqrt(net.n)), oracle.normalized_bcm(y0, net.k)], axis=1)
+    Qr = oracle.orth_iter(op, oracle.initial_q(C), 10)
+    ld = net.k + 1 + (-(net.k + 1)) % (2 if prm.q_dtype == "f64" else 4)
+    full = np.zeros((net.n, ld))
+    full[:, :net.k + 1] = Qr
+    T = torch.from_numpy(full).to(qdt(prm)).cuda()
+    lg, Rg, objg, itg = lib.discretize(T[:, 1:], net.k)
+    lr, Rr, objr, itr = oracle.discretize(T.cpu().double().numpy()[:, 1:net.k + 1])
+    agree = (lg.cpu().numpy() == lr).mean()
+    print(f"cfg {cfg}: label agreement {agree:.5f}, iters gpu {itg} oracle {itr}")
+    assert ari(lg.cpu().numpy(), lr) >= 0.99
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4])
+def test_cluster_end_to_end(lib, cfg):
+    net, prm, op, ki, ks = workload(cfg)
+    s, keep = lib.network(net)
+    params = lib.default_params(k=net.k, K=prm.K, alpha=prm.alpha, beta=prm.beta, gamma=prm.gamma, tau=prm.tau,
+                                T_i=prm.T_i, T_a=prm.T_a, eps_q=prm.eps_q, knn_mode=prm.knn_mode,
+                                q_dtype=prm.q_dtype)
+    lg, info = lib.cluster(s, params)
+    lg = lg.cpu().numpy()
+    lr, rep = oracle.cluster(op, net.k, alpha=prm.alpha, gamma=prm.gamma, tau=prm.tau, T_i=prm.T_i, T_a=prm.T_a,
+                             eps_q=prm.eps_q)
+    phi_g = oracle.mhc(op, lg, net.k, prm.alpha, prm.gamma)
+    a = ari(lg, lr)
+    print(f"cfg {cfg}: ARI(gpu, oracle)={a:.4f} phi gpu {phi_g:.6f} ({info['best_phi']:.6f} on device) "
+          f"oracle {rep.best_phi:.6f}; iters gpu {info['iterations']} ({info['stop_reason']}) oracle "
+          f"{rep.iterations} ({rep.reason}); ARI vs planted {ari(lg, net.labels):.3f}")
+    assert a >= 0.99
+    assert abs(phi_g - rep.best_phi) <= 1e-4 * rep.best_phi
+    assert abs(info["best_phi"] - phi_g) <= 1e-5 * phi_g
+    assert lg.min() >= 0 and lg.max() < net.k
+
+
+def test_cluster_deterministic(lib):
+    net, prm, op, ki, ks = workload(2)
+    s, keep = lib.network(net)
+    params = lib.default_params(k=net.k, K=prm.K, knn_mode=prm.knn_mode, q_dtype=prm.q_dtype)
+    a, ia = lib.cluster(s, params)
+    b, ib = lib.cluster(s, params)
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    assert ia["best_phi"] == ib["best_phi"] and ia["trace"] == ib["trace"]

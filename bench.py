@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Benchmark of the clustering hot path on one MI355X.
+
+One step = one whole clustering run through the C ABI (ancka_cluster): exact KNN graph over the
+attributes (BF16 MFMA tiles + FP64 rescoring), operator build, greedy initial BCM, orthogonal
+iteration with Cholesky QR, Discretize and MHC every tau iterations, early termination.  The
+workload is the n = 2.5M attributed graph (50 planted clusters, power-law SBM of mean degree 30,
+BF16 attributes d = 128 from a 50-component Gaussian mixture, K = 10), generated synthetically
+and resident in HBM before the timed region starts.
+
+stdout: one JSON line.  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cluster wall-s at n=2.5M; KNN TFLOP/s; SpMM HBM GB/s; warm vs cold iters"
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_HBM_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spmm_compulsory_bytes(info, n, L, kp, es=4):
+    """Compulsory bytes of one Z = P Q: topology indices + row pointers + per-segment scales,
+    KNN indices and values + row pointers, per-row self coefficient, Q read once, Z written once."""
+    topo = 4 * info["nnz_topo"] + 8 * (n * L + 1) + es * n * L
+    knn = (4 + es) * info["nnz_knn"] + 8 * (n + 1)
+    rows = es * n
+    blocks = 2 * es * n * kp
+    return topo + knn + rows + blocks
+
+
+def cpu_baseline(net, prm, gpu_iters, gpu_checks, knn_rows=96, small_scale=0.02):
+    """The FP64 oracle timed on a bounded sample of the workload, extrapolated to one run.
+
+    Sample: (a) exact KNN of `knn_rows` random query rows against all n candidates, scaled by
+    n / knn_rows; (b) the oracle's operator build, one orthogonal iteration, one Discretize and
+    one MHC on the same workload generated at `small_scale` (same distributions), scaled
+    linearly in n and by the GPU run's iteration and check counts."""
+    import oracle
+    from paper_2408_05459_amd import synth
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rng = np.random.default_rng(12345)
+    rows = np.sort(rng.choice(net.n, size=knn_rows, replace=False))
+    t0 = time.perf_counter()
+    oracle.knn(net.X, prm.K, rows=rows, block=32)
+    t_knn = (time.perf_counter() - t0) * net.n / knn_rows
+    small, sp = synth.make_config(4, scale=small_scale)
+    _, zero = oracle.normalize_rows(small.X)
+    ki, ks = oracle.knn(small.X, sp.K)
+    t0 = time.perf_counter()
+    op = oracle.build_operator(small.kind, small.n, small.ptrs, small.idxs, small.m, zero, ki, ks, sp.beta)
+    t_op = time.perf_counter() - t0
+    y0, _ = oracle.init_bcm(op, small.k, sp.alpha, sp.T_i)
+    C = np.concatenate([np.full((small.n, 1), 1 / math.sqrt(small.n)), oracle.normalized_bcm(y0, small.k)], axis=1)
+    Q = oracle.initial_q(C)
+    t0 = time.perf_counter()
+    Q, _ = oracle.qr_pos(oracle.apply_P(op, Q))
+    t_it = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    y, _, _, _ = oracle.discretize(Q[:, 1:])
+    t_disc = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.mhc(op, y, small.k, sp.alpha, sp.gamma)
+    t_mhc = time.perf_counter() - t0
+    f = net.n / small.n
+    total = t_knn + f * (t_op + gpu_iters * t_it + gpu_checks * (t_disc + t_mhc))
+    return {
+        "value": round(total, 1), "unit": "s", "cores": threads, "kind": "oracle",
+        "sample": (f"exact FP64 KNN of {knn_rows} random query rows against all {net.n} candidates scaled x"
+                   f"{net.n / knn_rows:.0f}; operator build + 1 orthogonal iteration + 1 Discretize + 1 MHC on "
+                   f"the same workload at n={small.n} scaled x{f:.0f} and by the GPU run's {gpu_iters} "
+                   f"iterations / {gpu_checks} checks"),
+        "phases_s": {"knn": round(t_knn, 1), "operator": round(f * t_op, 2),
+                     "iterations": round(f * gpu_iters * t_it, 2),
+                     "discretize+mhc": round(f * gpu_checks * (t_disc + t_mhc), 2)},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--spmm-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the method's multi-GPU sharding is "
+              f"described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2408_05459_amd import binding, synth
+
+    torch.cuda.set_device(0)
+    lib = binding.load()
+    t0 = time.perf_counter()
+    net, prm = synth.make_config(a.config, scale=a.scale)
+    log(f"generated {net.name} in {time.perf_counter() - t0:.1f}s")
+    s, keep = lib.network(net)
+    params = lib.default_params(k=net.k, K=prm.K, alpha=prm.alpha, beta=prm.beta, gamma=prm.gamma, tau=prm.tau,
+                                T_i=prm.T_i, T_a=prm.T_a, eps_q=prm.eps_q, knn_mode=prm.knn_mode,
+                                q_dtype=prm.q_dtype)
+    torch.cuda.synchronize()
+
+    for w in range(a.warmup):
+        _, info = lib.cluster(s, params)
+        log(f"warmup {w}: iterations {info['iterations']} phases {info['phase_ms']}")
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for st in range(a.steps):
+        labels, info = lib.cluster(s, params)
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / a.steps
+    for i, info in enumerate(infos):
+        log(f"step {i}: iterations {info['iterations']} ({info['stop_reason']}) best phi {info['best_phi']:.6f} "
+            f"phases {json.dumps({k: round(v, 1) for k, v in info['phase_ms'].items()})}")
+    last = infos[-1]
+    from sklearn.metrics import adjusted_rand_score
+    ari_planted = float(adjusted_rand_score(net.labels, labels.cpu().numpy()))
+
+    # ---- KNN tile kernel: algorithmic (unordered-pair) and executed FLOPs
+    n, d = net.n, net.d
+    tile_ms = float(np.mean([i["knn_tile_ms"] for i in infos]))
+    useful = float(n) * (n - 1) * d
+    executed = 2.0 * n * n * d
+    knn_useful_tf = useful / (tile_ms * 1e-3) / 1e12
+    knn_exec_tf = executed / (tile_ms * 1e-3) / 1e12
+
+    # ---- SpMM Z = P Q of the iteration, timed with HIP events on the library's stream
+    X = binding.upload_attributes(net.X, net.x_dtype)
+    nidx, nsim, _ = lib.knn(X, prm.K, prm.knn_mode)
+    op = lib.build_operator(s, nidx, nsim, prm.K, prm.beta, prm.q_dtype)
+    oinfo = op.info()
+    kp = net.k + 1
+    ld = kp + (-kp) % 4
+    Q = torch.randn((n, ld), dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        op.apply(Q)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(a.spmm_reps):
+        op.apply(Q)
+    e1.record()
+    torch.cuda.synchronize()
+    spmm_ms = e0.elapsed_time(e1) / a.spmm_reps
+    spmm_bytes = spmm_compulsory_bytes(oinfo, n, net.L, kp)
+    spmm_gbps = spmm_bytes / (spmm_ms * 1e-3) / 1e9
+    del X, nidx, nsim, op, Q
+    torch.cuda.empty_cache()
+
+    iters = last["iterations"]
+    spmm_total_ms = iters * spmm_ms
+    if tile_ms >= spmm_total_ms:
+        roof = {"kernel": "knn_bf16_kernel (similarity tiles + top-2K)", "bound": "mfma",
+                "achieved": round(knn_useful_tf, 1), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(knn_useful_tf / PEAK_BF16_TFLOPS, 4), "traffic": None}
+    else:
+        roof = {"kernel": "spmm_kernel (Z = P Q)", "bound": "hbm", "achieved": round(spmm_gbps, 1),
+                "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": round(spmm_gbps / PEAK_HBM_GBPS, 4), "traffic": None}
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms_per_step / 1000.0, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": net.name, "n": n, "k": net.k, "d": d, "K": prm.K,
+                   "nnz_topology": int(sum(int(p[-1]) for p in net.ptrs)),
+                   "precision": "KNN BF16 MFMA (FP32 accumulation) + FP64 rescoring; SpMM FP32; k x k FP64",
+                   "parallelism": "1 GPU"},
+        "roofline": roof,
+        "knn": {"tile_ms": round(tile_ms, 2), "tflops_useful": round(knn_useful_tf, 1),
+                "tflops_executed": round(knn_exec_tf, 1), "frac_executed": round(knn_exec_tf / PEAK_BF16_TFLOPS, 4),
+                "uncertified_rows": last["knn_uncertified_rows"], "call_ms": round(last["knn_total_ms"], 2)},
+        "spmm": {"ms": round(spmm_ms, 3), "compulsory_bytes": spmm_bytes, "gbps_compulsory": round(spmm_gbps, 1),
+                 "frac": round(spmm_gbps / PEAK_HBM_GBPS, 4), "nnz_topology": oinfo["nnz_topo"],
+                 "nnz_knn": oinfo["nnz_knn"], "cols": kp},
+        "phases_ms": {k_: round(v, 1) for k_, v in last["phase_ms"].items()},
+        "iterations": iters,
+        "stop_reason": last["stop_reason"],
+        "best_phi": last["best_phi"],
+        "ari_vs_planted": round(ari_planted, 4),
+    }
+    if not a.no_cpu_baseline:
+        log("timing the oracle on a bounded sample ...")
+        checks = sum(1 for t, _ in last["trace"] if t > 0)
+        out["cpu_baseline"] = cpu_baseline(net, prm, iters, checks)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

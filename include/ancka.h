@@ -96,6 +96,8 @@ typedef struct {
   int64_t zero_rows;         /* attribute rows that are all zero */
   int64_t uncertified_rows;  /* rows whose 2K candidate list could not prove the top-K */
   int64_t recomputed_rows;   /* rows recomputed exactly (= uncertified_rows) */
+  double tile_ms;            /* duration of the similarity-tile + top-K kernel (HIP events on the stream) */
+  double total_ms;           /* duration of the whole ancka_knn call on the stream */
 } ancka_knn_stats;
 
 enum { ANCKA_PHASE_KNN = 0, ANCKA_PHASE_OPERATOR = 1, ANCKA_PHASE_INIT = 2, ANCKA_PHASE_ITER = 3,

@@ -43,7 +43,8 @@ class ancka_params(C.Structure):
 
 
 class ancka_knn_stats(C.Structure):
-    _fields_ = [("zero_rows", C.c_int64), ("uncertified_rows", C.c_int64), ("recomputed_rows", C.c_int64)]
+    _fields_ = [("zero_rows", C.c_int64), ("uncertified_rows", C.c_int64), ("recomputed_rows", C.c_int64),
+                ("tile_ms", C.c_double), ("total_ms", C.c_double)]
 
 
 class ancka_report(C.Structure):
@@ -231,6 +232,7 @@ class Lib:
             "trace": [(tt[i], tp[i]) for i in range(m)],
             "phase_ms": {PHASES[i]: rep.phase_ms[i] for i in range(ANCKA_NPHASES)},
             "knn_zero_rows": rep.knn.zero_rows, "knn_uncertified_rows": rep.knn.uncertified_rows,
+            "knn_tile_ms": rep.knn.tile_ms, "knn_total_ms": rep.knn.total_ms,
             "disc_iters_total": rep.disc_iters_total,
         }
         return labels, info

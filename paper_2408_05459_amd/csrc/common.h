@@ -27,7 +27,12 @@ struct ancka_ctx {
   int num_cu = 0;
   std::string err;
   std::map<std::string, DevBuf> ws;   // grow-only named workspaces
+  hipEvent_t ev[8] = {};               // timing events, created on first use
+  bool ev_ready = false;
 };
+
+// the context's timing events (created once)
+ancka_status ctx_events(ancka_ctx* ctx, hipEvent_t** out);
 
 struct ancka_op {
   int kind = 0;

@@ -34,6 +34,15 @@ ancka_status ws_get(ancka_ctx* ctx, const char* name, size_t bytes, void** out) 
   return ANCKA_OK;
 }
 
+ancka_status ctx_events(ancka_ctx* ctx, hipEvent_t** out) {
+  if (!ctx->ev_ready) {
+    for (auto& e : ctx->ev) HIP_TRY(ctx, hipEventCreate(&e));
+    ctx->ev_ready = true;
+  }
+  *out = ctx->ev;
+  return ANCKA_OK;
+}
+
 ancka_status op_alloc(ancka_ctx* ctx, ancka_op* op, size_t bytes, void** out) {
   if (bytes == 0) bytes = 256;
   void* p = nullptr;
@@ -77,6 +86,8 @@ void ancka_destroy(ancka_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (auto& kv : ctx->ws)
     if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+  if (ctx->ev_ready)
+    for (auto& e : ctx->ev) (void)hipEventDestroy(e);
   delete ctx;
 }
 

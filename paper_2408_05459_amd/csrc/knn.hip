@@ -73,19 +73,6 @@ __global__ __launch_bounds__(256) void knn_prologue_kernel(const TX* __restrict_
   }
 }
 
-// per tile of `tile` candidate rows: the smallest norm of a non-zero row (+inf if none)
-__global__ void tile_min_norm_kernel(const float* __restrict__ nrm, int64_t n, int tile, float* __restrict__ out,
-                                     int64_t ntiles) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntiles) return;
-  float m = INFINITY;
-  for (int64_t j = t * tile; j < n && j < (t + 1) * tile; j++) {
-    const float v = nrm[j];
-    if (v > 0.0f && v < m) m = v;
-  }
-  out[t] = m;
-}
-
 // ---- exact tiles with vector FMA (EXACT_F64 / EXACT_F32) -----------------------------------
 // 64 queries x 64 candidates per step, 4x4 outputs per thread, d streamed in chunks of 16.
 // The score tile goes to LDS; thread r < 64 owns query r's list of length KP (sorted).
@@ -202,19 +189,40 @@ __global__ __launch_bounds__(256) void knn_vector_kernel(const TX* __restrict__ 
 }
 
 // ---- BF16 MFMA tiles ------------------------------------------------------------------------
-// Workgroup = 4 waves; wave w owns QW queries (QW/32 column blocks of the 32x32 MFMA output),
-// held in registers as B operands for the whole kernel.  Candidate tiles of 64 rows (two 32-row
-// A blocks) stream through double-buffered LDS.  Epilogue: a lane holds 16 candidates of one
-// query per (A block, B block); their maximum is compared with the query's threshold scaled by
-// the tile's smallest norm (a necessary condition), and only then are candidates scored exactly
-// (dot * 1/|x_j|) and inserted into the query's sorted list in LDS.
+// Scan order.  Rows are grouped into coarse cells (the most similar of NPIV pivot rows) and,
+// inside a cell, ordered by norm; queries and candidates share this order (a bf16 copy Xs).  A
+// workgroup owns 4*QW consecutive queries -- mostly one cell -- and scans every candidate tile
+// once, starting with the first tile of its own cell and wrapping around.  The order changes
+// nothing in the result (every candidate is scored; lists are ordered by the (similarity,
+// index) key) but it makes each query's running threshold nearly final after its own cell, so
+// later tiles seldom reach the insertion path.
+// Tiles.  Wave w holds its QW queries as MFMA B operands in registers for the whole kernel;
+// 64-row candidate tiles (two 32-row A blocks) stream through double-buffered LDS.
+// Epilogue.  A lane holds 16 candidates of one query per (A block, B block).  The maximum raw
+// dot of its 32 candidates is compared with the query's threshold times the tile's smallest
+// norm -- necessary for any of them to enter the list, and tight because a tile's norms are
+// close.  Passing lanes score their candidates exactly (dot / |x_j|) and insert them into the
+// query's sorted list in LDS; the two half-waves, which hold different candidates of the same
+// queries, insert one after the other.
 constexpr int BT_C = 64;   // candidates per tile
+constexpr int NPIV = 64;   // coarse cells of the scan order
 
-template <int DP, int QW>
-__global__ __launch_bounds__(256, 1) void knn_bf16_kernel(const uint16_t* __restrict__ Xp, int64_t n,
-                                                          const float* __restrict__ invn,
-                                                          const float* __restrict__ tile_min, int KP,
-                                                          int32_t* __restrict__ cand_idx, float* __restrict__ cand_sim) {
+__device__ __noinline__ void insert_sorted(float* ls, int* li, int KP, float s, int jj) {
+  int p = KP - 1;
+  while (p > 0 && better<float>(s, jj, ls[p - 1], li[p - 1])) {
+    ls[p] = ls[p - 1];
+    li[p] = li[p - 1];
+    p--;
+  }
+  ls[p] = s;
+  li[p] = jj;
+}
+
+template <int DP, int QW, int NBUF>
+__global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
+    const uint16_t* __restrict__ Xs, int64_t n, const float* __restrict__ invs, const int32_t* __restrict__ perm,
+    const float* __restrict__ tile_min, const int32_t* __restrict__ wg_start, int KP, int32_t* __restrict__ cand_idx,
+    float* __restrict__ cand_sim) {
   constexpr int KS = DP / 16;           // MFMA k-steps
   constexpr int NQB = QW / 32;          // query blocks per wave
   constexpr int QB = 4 * QW;            // queries per workgroup
@@ -224,9 +232,11 @@ __global__ __launch_bounds__(256, 1) void knn_bf16_kernel(const uint16_t* __rest
   static_assert(CHUNKS % 256 == 0, "tile chunks");
 
   extern __shared__ __align__(16) unsigned char smem[];
-  uint16_t* tileb = (uint16_t*)smem;                         // [2][BT_C][LDR]
-  float* tinv = (float*)(tileb + 2 * BT_C * LDR);            // [2][BT_C]
-  float* lsim = tinv + 2 * BT_C;                             // [QB][KP]
+  uint16_t* tileb = (uint16_t*)smem;                         // [NBUF][BT_C][LDR]
+  float* tinv = (float*)(tileb + NBUF * BT_C * LDR);         // [NBUF][BT_C]
+  int* tperm = (int*)(tinv + NBUF * BT_C);                   // [NBUF][BT_C]
+  float* tmn = (float*)(tperm + NBUF * BT_C);                // [NBUF] (padded to 4)
+  float* lsim = tmn + 4;                                     // [QB][KP]
   int* lidx = (int*)(lsim + QB * KP);                        // [QB][KP]
 
   const int tid = threadIdx.x;
@@ -245,17 +255,18 @@ __global__ __launch_bounds__(256, 1) void knn_bf16_kernel(const uint16_t* __rest
   bf16x8 bq[NQB][KS];
   float thr[NQB];
   int qloc[NQB];
-  int64_t qglob[NQB];
+  int qorig[NQB];
 #pragma unroll
   for (int qb = 0; qb < NQB; qb++) {
     qloc[qb] = wave * QW + qb * 32 + l32;
-    qglob[qb] = q0 + qloc[qb];
-    const bool valid = qglob[qb] < n && invn[qglob[qb] < n ? qglob[qb] : 0] > 0.0f;
-    thr[qb] = valid ? -INFINITY : INFINITY;
+    const int64_t qs = q0 + qloc[qb];
+    const bool inb = qs < n;
+    qorig[qb] = inb ? perm[qs] : -1;
+    thr[qb] = (inb && invs[inb ? qs : 0] > 0.0f) ? -INFINITY : INFINITY;
 #pragma unroll
     for (int ks = 0; ks < KS; ks++) {
-      if (qglob[qb] < n) {
-        const uint4 v = *(const uint4*)(Xp + qglob[qb] * DP + ks * 16 + half * 8);
+      if (inb) {
+        const uint4 v = *(const uint4*)(Xs + qs * DP + ks * 16 + half * 8);
         bq[qb][ks] = __builtin_bit_cast(bf16x8, v);
       } else {
         bq[qb][ks] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
@@ -264,19 +275,24 @@ __global__ __launch_bounds__(256, 1) void knn_bf16_kernel(const uint16_t* __rest
   }
 
   const int64_t ntiles = cdiv(n, BT_C);
+  const int64_t t0 = wg_start[blockIdx.x];
   uint4 pre[CPT];
   float pre_inv = 0.0f;
-  auto prefetch = [&](int64_t t) {
+  int pre_perm = -1;
+  float pre_tmn = INFINITY;
+  auto prefetch = [&](int64_t tt) {
+    if (tid == 0) pre_tmn = tile_min[tt];
 #pragma unroll
     for (int u = 0; u < CPT; u++) {
       const int c = u * 256 + tid;
       const int r = c / (DP / 8), c8 = c % (DP / 8);
-      const int64_t j = t * BT_C + r;
-      pre[u] = (j < n) ? *(const uint4*)(Xp + j * DP + c8 * 8) : make_uint4(0, 0, 0, 0);
+      const int64_t j = tt * BT_C + r;
+      pre[u] = (j < n) ? *(const uint4*)(Xs + j * DP + c8 * 8) : make_uint4(0, 0, 0, 0);
     }
     if (tid < BT_C) {
-      const int64_t j = t * BT_C + tid;
-      pre_inv = (j < n) ? invn[j] : 0.0f;
+      const int64_t j = tt * BT_C + tid;
+      pre_inv = (j < n) ? invs[j] : 0.0f;
+      pre_perm = (j < n) ? perm[j] : -1;
     }
   };
   auto commit = [&](int buf) {
@@ -286,16 +302,24 @@ __global__ __launch_bounds__(256, 1) void knn_bf16_kernel(const uint16_t* __rest
       const int r = c / (DP / 8), c8 = c % (DP / 8);
       *(uint4*)(tileb + (buf * BT_C + r) * LDR + c8 * 8) = pre[u];
     }
-    if (tid < BT_C) tinv[buf * BT_C + tid] = pre_inv;
+    if (tid < BT_C) {
+      tinv[buf * BT_C + tid] = pre_inv;
+      tperm[buf * BT_C + tid] = pre_perm;
+    }
+    if (tid == 0) tmn[buf] = pre_tmn;
+  };
+  auto tile_at = [&](int64_t t) {
+    int64_t tt = t0 + t;
+    return tt >= ntiles ? tt - ntiles : tt;
   };
 
-  prefetch(0);
+  prefetch(tile_at(0));
   commit(0);
   __syncthreads();
 
   for (int64_t t = 0; t < ntiles; t++) {
-    const int buf = (int)(t & 1);
-    if (t + 1 < ntiles) prefetch(t + 1);
+    const int buf = NBUF == 2 ? (int)(t & 1) : 0;
+    if (t + 1 < ntiles) prefetch(tile_at(t + 1));
 
     f32x16 acc[2][NQB];
 #pragma unroll
@@ -322,7 +346,7 @@ __global__ __launch_bounds__(256, 1) void knn_bf16_kernel(const uint16_t* __rest
     }
 
     // ---- epilogue: filter, then exact insertion for the rare hits
-    const float mn = tile_min[t];
+    const float mn = tmn[buf];
 #pragma unroll
     for (int qb = 0; qb < NQB; qb++) {
       float m = -INFINITY;
@@ -335,7 +359,7 @@ __global__ __launch_bounds__(256, 1) void knn_bf16_kernel(const uint16_t* __rest
       const bool hit = m >= fth;
       if (__ballot(hit)) {
         const int q = qloc[qb];
-        const int64_t qi = qglob[qb];
+        const int qi = qorig[qb];
         float* ls = lsim + q * KP;
         int* li = lidx + q * KP;
         for (int h = 0; h < 2; h++) {
@@ -345,23 +369,20 @@ __global__ __launch_bounds__(256, 1) void knn_bf16_kernel(const uint16_t* __rest
 #pragma unroll
             for (int cb = 0; cb < 2; cb++) {
 #pragma unroll
-              for (int i = 0; i < 16; i++) {
-                const int cl = cb * 32 + 8 * (i / 4) + 4 * half + (i % 4);
-                const int64_t j = t * BT_C + cl;
-                const float iv = tinv[buf * BT_C + cl];
-                const float s = acc[cb][qb][i] * iv;
-                const int jj = (int)j;
-                if (iv > 0.0f && j != qi && better<float>(s, jj, tcur, tcur_i)) {
-                  int p = KP - 1;
-                  while (p > 0 && better<float>(s, jj, ls[p - 1], li[p - 1])) {
-                    ls[p] = ls[p - 1];
-                    li[p] = li[p - 1];
-                    p--;
+              for (int g = 0; g < 4; g++) {
+                const int cl0 = cb * 32 + 8 * g + 4 * half;
+                const float4 iv4 = *(const float4*)(tinv + buf * BT_C + cl0);
+                const int4 jp4 = *(const int4*)(tperm + buf * BT_C + cl0);
+                const float ivs[4] = {iv4.x, iv4.y, iv4.z, iv4.w};
+                const int jps[4] = {jp4.x, jp4.y, jp4.z, jp4.w};
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                  const float s = acc[cb][qb][4 * g + e] * ivs[e];
+                  if (ivs[e] > 0.0f && jps[e] != qi && better<float>(s, jps[e], tcur, tcur_i)) {
+                    insert_sorted(ls, li, KP, s, jps[e]);
+                    tcur = ls[KP - 1];
+                    tcur_i = li[KP - 1];
                   }
-                  ls[p] = s;
-                  li[p] = jj;
-                  tcur = ls[KP - 1];
-                  tcur_i = li[KP - 1];
                 }
               }
             }
@@ -372,23 +393,130 @@ __global__ __launch_bounds__(256, 1) void knn_bf16_kernel(const uint16_t* __rest
       }
     }
 
-    if (t + 1 < ntiles) commit(buf ^ 1);
-    __syncthreads();
-  }
-
-  // write the lists (scores scaled by 1/|x_i| to cosine)
-#pragma unroll
-  for (int qb = 0; qb < NQB; qb++) {
-    const int64_t qi = qglob[qb];
-    if (qi >= n || half != 0) continue;
-    const float iq = invn[qi];
-    const int q = qloc[qb];
-    for (int r = 0; r < KP; r++) {
-      const int j = lidx[q * KP + r];
-      cand_idx[qi * KP + r] = (j == INT_MAX) ? -1 : j;
-      cand_sim[qi * KP + r] = (j == INT_MAX) ? 0.0f : lsim[q * KP + r] * iq;
+    if (NBUF == 2) {
+      if (t + 1 < ntiles) commit(buf ^ 1);
+      __syncthreads();
+    } else {
+      __syncthreads();            // every wave is done with the single buffer
+      if (t + 1 < ntiles) commit(0);
+      __syncthreads();
     }
   }
+
+  // write the lists (one thread per query), scores scaled by 1/|x_i| to cosines
+  for (int q = tid; q < QB; q += 256) {
+    const int64_t qs = q0 + q;
+    if (qs >= n) continue;
+    const int qi = perm[qs];
+    const float iq = invs[qs];
+    for (int r = 0; r < KP; r++) {
+      const int j = lidx[q * KP + r];
+      cand_idx[(int64_t)qi * KP + r] = (j == INT_MAX) ? -1 : j;
+      cand_sim[(int64_t)qi * KP + r] = (j == INT_MAX) ? 0.0f : lsim[q * KP + r] * iq;
+    }
+  }
+}
+
+// cell of each row: the most similar of NPIV pivot rows (dot with the pivot scaled by its inverse
+// norm; ties to the smaller pivot).  Pivots are held in LDS as bf16; a thread owns a row and
+// sweeps it 8 elements at a time against every pivot.
+__global__ __launch_bounds__(256) void cell_assign_kernel(const uint16_t* __restrict__ X, int64_t n, int64_t d,
+                                                          int64_t ldx, const float* __restrict__ invn,
+                                                          const int64_t* __restrict__ piv, uint64_t* __restrict__ keys,
+                                                          const float* __restrict__ nrm, uint64_t* __restrict__ vals) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int dp = (int)((d + 7) / 8 * 8);
+  uint16_t* P = (uint16_t*)smem;            // [NPIV][dp]
+  float* pinv = (float*)(P + NPIV * dp);    // [NPIV]
+  for (int e = threadIdx.x; e < NPIV * dp; e += 256) {
+    const int p = e / dp, c = e % dp;
+    P[e] = (c < d) ? X[piv[p] * ldx + c] : (uint16_t)0;
+  }
+  if (threadIdx.x < NPIV) pinv[threadIdx.x] = invn[piv[threadIdx.x]];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float acc[NPIV];
+#pragma unroll
+  for (int p = 0; p < NPIV; p++) acc[p] = 0.0f;
+  const uint16_t* xr = X + i * ldx;
+  for (int c0 = 0; c0 < dp; c0 += 8) {
+    float xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) xv[u] = (c0 + u < d) ? bf16_to_f32(xr[c0 + u]) : 0.0f;
+#pragma unroll
+    for (int p = 0; p < NPIV; p++) {
+      const uint4 pv = *(const uint4*)(P + p * dp + c0);
+      const uint32_t w[4] = {pv.x, pv.y, pv.z, pv.w};
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        acc[p] = fmaf(xv[2 * u], __uint_as_float(w[u] << 16), acc[p]);
+        acc[p] = fmaf(xv[2 * u + 1], __uint_as_float(w[u] & 0xffff0000u), acc[p]);
+      }
+    }
+  }
+  int best = 0;
+  float bv = acc[0] * pinv[0];
+#pragma unroll
+  for (int p = 1; p < NPIV; p++) {
+    const float v = acc[p] * pinv[p];
+    if (v > bv) {
+      bv = v;
+      best = p;
+    }
+  }
+  keys[i] = ((uint64_t)best << 32) | (uint64_t)__float_as_uint(nrm[i]);
+  vals[i] = (uint64_t)i;
+}
+
+// Xs[p] = zero-padded bf16 row X[perm[p]], invs[p] = 1/|x_perm[p]|, perm[p]
+__global__ __launch_bounds__(256) void gather_sorted_kernel(const uint16_t* __restrict__ X, int64_t n, int64_t d,
+                                                            int64_t ldx, const uint64_t* __restrict__ order,
+                                                            const float* __restrict__ invn, int DP,
+                                                            uint16_t* __restrict__ Xs, float* __restrict__ invs,
+                                                            int32_t* __restrict__ perm) {
+  const int64_t p = (int64_t)blockIdx.x * 4 + threadIdx.x / ANCKA_WAVE;
+  const int lane = threadIdx.x % ANCKA_WAVE;
+  if (p >= n) return;
+  const int64_t i = (int64_t)order[p];
+  const uint16_t* xr = X + i * ldx;
+  uint16_t* xs = Xs + p * (int64_t)DP;
+  for (int c = lane; c < DP; c += ANCKA_WAVE) xs[c] = (c < d) ? xr[c] : (uint16_t)0;
+  if (lane == 0) {
+    invs[p] = invn[i];
+    perm[p] = (int32_t)i;
+  }
+}
+
+// per tile of ordered candidates: the smallest norm of a non-zero row (+inf if none)
+__global__ void tile_min_sorted_kernel(const float* __restrict__ invs, int64_t n, int tile, float* __restrict__ out,
+                                       int64_t ntiles) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  float m = INFINITY;
+  for (int64_t j = t * tile; j < n && j < (t + 1) * tile; j++) {
+    const float iv = invs[j];
+    if (iv > 0.0f) m = fminf(m, 1.0f / iv);
+  }
+  // 1/iv rounds; shrink by a few ulps so the bound stays below every |x_j| as seen through 1/|x_j|
+  out[t] = m * (1.0f - 4e-7f);
+}
+
+// first tile of each workgroup's scan: the tile holding the first row of the cell of its first
+// query (sorted keys carry the cell in bits 32..)
+__global__ void wg_start_kernel(const uint64_t* __restrict__ keys, int64_t n, int qb, int64_t nwg,
+                                int32_t* __restrict__ start) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nwg) return;
+  const uint64_t cell = keys[b * qb] >> 32;
+  const uint64_t target = cell << 32;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < target) lo = mid + 1;
+    else hi = mid;
+  }
+  start[b] = (int32_t)(lo / BT_C);
 }
 
 // ---- FP64 rescoring of the candidate lists + certificate --------------------------------------
@@ -552,30 +680,37 @@ ancka_status run_vector(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64
 }
 
 template <int DP, int QW>
-ancka_status run_bf16_t(ancka_ctx* ctx, const uint16_t* Xp, int64_t n, const float* invn, const float* tmin, int KP,
-                        int32_t* cidx, float* csim) {
+constexpr int bf16_qb() {
+  return 4 * QW;
+}
+int bf16_qw(int DP) { return DP <= 256 ? 64 : 32; }
+
+template <int DP, int QW, int NBUF>
+ancka_status run_bf16_t(ancka_ctx* ctx, const uint16_t* Xs, int64_t n, const float* invs, const int32_t* perm,
+                        const float* tmin, const int32_t* wg_start, int KP, int32_t* cidx, float* csim) {
   constexpr int QB = 4 * QW;
-  const size_t sm = (size_t)2 * BT_C * (DP + 8) * 2 + 2 * BT_C * 4 + (size_t)QB * KP * 8;
+  const size_t sm = (size_t)NBUF * BT_C * (DP + 8) * 2 + 2 * NBUF * BT_C * 4 + 16 + (size_t)QB * KP * 8;
   static bool attr_set = false;
   if (!attr_set) {
-    HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_bf16_kernel<DP, QW>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     160 * 1024));
+    HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_bf16_kernel<DP, QW, NBUF>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     attr_set = true;
   }
   if (sm > 160 * 1024) return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "knn: LDS budget exceeded (d=%d, K'=%d)", DP, KP);
-  knn_bf16_kernel<DP, QW><<<(unsigned)cdiv(n, QB), 256, sm, ctx->stream>>>(Xp, n, invn, tmin, KP, cidx, csim);
+  knn_bf16_kernel<DP, QW, NBUF><<<(unsigned)cdiv(n, QB), 256, sm, ctx->stream>>>(Xs, n, invs, perm, tmin, wg_start, KP,
+                                                                                  cidx, csim);
   LAUNCH_CHECK(ctx);
   return ANCKA_OK;
 }
 
-ancka_status run_bf16(ancka_ctx* ctx, int DP, const uint16_t* Xp, int64_t n, const float* invn, const float* tmin,
-                      int KP, int32_t* cidx, float* csim) {
+ancka_status run_bf16(ancka_ctx* ctx, int DP, const uint16_t* Xs, int64_t n, const float* invs, const int32_t* perm,
+                      const float* tmin, const int32_t* wg_start, int KP, int32_t* cidx, float* csim) {
   switch (DP) {
-    case 32: return run_bf16_t<32, 64>(ctx, Xp, n, invn, tmin, KP, cidx, csim);
-    case 64: return run_bf16_t<64, 64>(ctx, Xp, n, invn, tmin, KP, cidx, csim);
-    case 128: return run_bf16_t<128, 64>(ctx, Xp, n, invn, tmin, KP, cidx, csim);
-    case 256: return run_bf16_t<256, 64>(ctx, Xp, n, invn, tmin, KP, cidx, csim);
-    case 512: return run_bf16_t<512, 32>(ctx, Xp, n, invn, tmin, KP, cidx, csim);
+    case 32: return run_bf16_t<32, 64, 2>(ctx, Xs, n, invs, perm, tmin, wg_start, KP, cidx, csim);
+    case 64: return run_bf16_t<64, 64, 2>(ctx, Xs, n, invs, perm, tmin, wg_start, KP, cidx, csim);
+    case 128: return run_bf16_t<128, 64, 2>(ctx, Xs, n, invs, perm, tmin, wg_start, KP, cidx, csim);
+    case 256: return run_bf16_t<256, 64, 2>(ctx, Xs, n, invs, perm, tmin, wg_start, KP, cidx, csim);
+    case 512: return run_bf16_t<512, 32, 1>(ctx, Xs, n, invs, perm, tmin, wg_start, KP, cidx, csim);
     default: return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "knn: bf16 path supports d <= 512 (got padded %d)", DP);
   }
 }
@@ -620,20 +755,23 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
   ST_TRY(ws_get_t(ctx, "knn_nrm", (size_t)n, &nrm));
   ST_TRY(ws_get_t(ctx, "knn_zero", 2, &zc));
   ST_TRY(fill_zero(ctx, zc, 16));
-  uint16_t* Xp = nullptr;
   int DP = 0;
   if (mode == ANCKA_KNN_BF16_RESCORE) {
     DP = 32;
     while (DP < d) DP *= 2;
     if (DP > 512) return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "knn: bf16 path supports d <= 512");
-    ST_TRY(ws_get_t(ctx, "knn_xp", (size_t)n * DP, &Xp));
   }
-  knn_prologue_kernel<TX><<<(unsigned)cdiv(n, 4), 256, 0, ctx->stream>>>(X, n, d, ldx, sq, invn, nrm, Xp, DP, zc);
+  hipEvent_t* ev = nullptr;
+  ST_TRY(ctx_events(ctx, &ev));
+  HIP_TRY(ctx, hipEventRecord(ev[0], ctx->stream));
+  knn_prologue_kernel<TX><<<(unsigned)cdiv(n, 4), 256, 0, ctx->stream>>>(X, n, d, ldx, sq, invn, nrm, nullptr, 0, zc);
   LAUNCH_CHECK(ctx);
 
   if (mode == ANCKA_KNN_EXACT_F64) {
     int KP = K;
+    HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
     ST_TRY(run_vector<TX>(ctx, X, n, d, ldx, sq, invn, KP, true, nbr_idx, nbr_sim));
+    HIP_TRY(ctx, hipEventRecord(ev[2], ctx->stream));
     if (st) st->uncertified_rows = st->recomputed_rows = 0;
   } else {
     const int KP = 2 * K;
@@ -642,22 +780,67 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
     ST_TRY(ws_get_t(ctx, "knn_cidx", (size_t)n * KP, &cidx));
     ST_TRY(ws_get_t(ctx, "knn_csim", (size_t)n * KP, &csim));
     if (mode == ANCKA_KNN_EXACT_F32) {
+      HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
       ST_TRY(run_vector<TX>(ctx, X, n, d, ldx, sq, invn, KP, false, cidx, csim));
+      HIP_TRY(ctx, hipEventRecord(ev[2], ctx->stream));
     } else {
+      // scan order: rows grouped by coarse cell (nearest of NPIV pivot rows), by norm inside a
+      // cell; a zero-padded bf16 copy Xs in that order serves as queries and candidates
       const int64_t nt = cdiv(n, BT_C);
-      float* tmin = nullptr;
+      const int QB = 4 * bf16_qw(DP);
+      const int64_t nwg = cdiv(n, QB);
+      float *tmin = nullptr, *invs = nullptr;
+      uint64_t *keys = nullptr, *order = nullptr;
+      int64_t* piv = nullptr;
+      int32_t *perm = nullptr, *wgs = nullptr;
+      uint16_t* Xs = nullptr;
       ST_TRY(ws_get_t(ctx, "knn_tmin", (size_t)nt, &tmin));
-      tile_min_norm_kernel<<<(unsigned)cdiv(nt, 256), 256, 0, ctx->stream>>>(nrm, n, BT_C, tmin, nt);
+      ST_TRY(ws_get_t(ctx, "knn_keys", (size_t)n, &keys));
+      ST_TRY(ws_get_t(ctx, "knn_order", (size_t)n, &order));
+      ST_TRY(ws_get_t(ctx, "knn_piv", NPIV, &piv));
+      ST_TRY(ws_get_t(ctx, "knn_invs", (size_t)n, &invs));
+      ST_TRY(ws_get_t(ctx, "knn_perm", (size_t)n, &perm));
+      ST_TRY(ws_get_t(ctx, "knn_wgs", (size_t)nwg, &wgs));
+      ST_TRY(ws_get_t(ctx, "knn_xs", (size_t)n * DP, &Xs));
+      // pivots: evenly spaced rows (a zero pivot row only yields an unused cell)
+      int64_t hp[NPIV];
+      for (int p = 0; p < NPIV; p++) hp[p] = (int64_t)((double)p * (double)n / NPIV);
+      HIP_TRY(ctx, hipMemcpyAsync(piv, hp, sizeof(hp), hipMemcpyHostToDevice, ctx->stream));
+      const size_t csm = (size_t)NPIV * ((d + 7) / 8 * 8) * 2 + NPIV * 4;
+      static bool cattr = false;
+      if (!cattr) {
+        HIP_TRY(ctx, hipFuncSetAttribute((const void*)cell_assign_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         160 * 1024));
+        cattr = true;
+      }
+      cell_assign_kernel<<<(unsigned)cdiv(n, 256), 256, csm, ctx->stream>>>((const uint16_t*)(const void*)X, n, d, ldx,
+                                                                            invn, piv, keys, nrm, order);
       LAUNCH_CHECK(ctx);
-      ST_TRY(run_bf16(ctx, DP, Xp, n, invn, tmin, KP, cidx, csim));
+      ST_TRY(radix_sort_u64(ctx, keys, order, n, 40));
+      gather_sorted_kernel<<<(unsigned)cdiv(n, 4), 256, 0, ctx->stream>>>((const uint16_t*)(const void*)X, n, d, ldx,
+                                                                          order, invn, DP, Xs, invs, perm);
+      LAUNCH_CHECK(ctx);
+      tile_min_sorted_kernel<<<(unsigned)cdiv(nt, 256), 256, 0, ctx->stream>>>(invs, n, BT_C, tmin, nt);
+      LAUNCH_CHECK(ctx);
+      wg_start_kernel<<<(unsigned)cdiv(nwg, 256), 256, 0, ctx->stream>>>(keys, n, QB, nwg, wgs);
+      LAUNCH_CHECK(ctx);
+      HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
+      ST_TRY(run_bf16(ctx, DP, Xs, n, invs, perm, tmin, wgs, KP, cidx, csim));
+      HIP_TRY(ctx, hipEventRecord(ev[2], ctx->stream));
     }
     ST_TRY(rescore_and_fix<TX>(ctx, X, n, d, ldx, sq, KP, K, cidx, csim, nbr_idx, (float*)nbr_sim, st));
   }
+  HIP_TRY(ctx, hipEventRecord(ev[3], ctx->stream));
   if (st) {
     unsigned long long hz = 0;
     HIP_TRY(ctx, hipMemcpyAsync(&hz, zc, sizeof(hz), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     st->zero_rows = (int64_t)hz;
+    float a = 0.f, b = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&a, ev[1], ev[2]));
+    HIP_TRY(ctx, hipEventElapsedTime(&b, ev[0], ev[3]));
+    st->tile_ms = a;
+    st->total_ms = b;
   }
   return ANCKA_OK;
 }
@@ -675,7 +858,7 @@ extern "C" ancka_status ancka_knn(ancka_ctx* ctx, const void* X, int32_t xdtype,
   if (mode == ANCKA_KNN_BF16_RESCORE && xdtype != ANCKA_BF16)
     return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "ancka_knn: BF16_RESCORE needs bf16 attributes");
   if (mode < 0 || mode > 2) return set_err(ctx, ANCKA_ERR_INVALID_ARG, "ancka_knn: unknown mode %d", mode);
-  if (stats) *stats = ancka_knn_stats{0, 0, 0};
+  if (stats) *stats = ancka_knn_stats{0, 0, 0, 0.0, 0.0};
   switch (xdtype) {
     case ANCKA_F64: return knn_typed<double>(ctx, (const double*)X, n, d, ldx, K, mode, nbr_idx, nbr_sim, stats);
     case ANCKA_F32: return knn_typed<float>(ctx, (const float*)X, n, d, ldx, K, mode, nbr_idx, nbr_sim, stats);

@@ -327,16 +327,22 @@ __global__ void build_q0_kernel(T* __restrict__ Q, int64_t n, int k, int64_t ld,
   for (int64_t j = k + 1; j < ld; j++) Q[i * ld + j] = (T)0;
 }
 
-__global__ void count_labels_kernel(const int32_t* __restrict__ labels, int64_t n, int k, int32_t* __restrict__ counts,
-                                    int* __restrict__ bad) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int l = labels[i];
-  if (l < 0 || l >= k) {
-    atomicOr(bad, 1);
-    return;
+// per-block histogram in LDS, then one global add per non-empty bin (integer: order-free)
+__global__ __launch_bounds__(256) void count_labels_kernel(const int32_t* __restrict__ labels, int64_t n, int k,
+                                                           int32_t* __restrict__ counts, int* __restrict__ bad) {
+  __shared__ int h[64];
+  if (threadIdx.x < 64) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * 4096;
+  for (int u = 0; u < 16; u++) {
+    const int64_t i = base + (int64_t)u * 256 + threadIdx.x;
+    if (i >= n) break;
+    const int l = labels[i];
+    if (l < 0 || l >= k) atomicOr(bad, 1);
+    else atomicAdd(&h[l], 1);
   }
-  atomicAdd(&counts[l], 1);
+  __syncthreads();
+  if ((int)threadIdx.x < k && h[threadIdx.x] != 0) atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
 }
 
 }  // namespace
@@ -352,7 +358,7 @@ ancka_status qr_block(ancka_ctx* ctx, int dtype, const void* Z, void* Qout, int6
 // counts[c] = |{i : labels[i] = c}| (device); *bad set for out-of-range labels
 ancka_status count_labels(ancka_ctx* ctx, const int32_t* labels, int64_t n, int k, int32_t* counts, int* bad) {
   ST_TRY(fill_zero(ctx, counts, sizeof(int32_t) * k));
-  count_labels_kernel<<<(unsigned)cdiv(n, 256), 256, 0, ctx->stream>>>(labels, n, k, counts, bad);
+  count_labels_kernel<<<(unsigned)cdiv(n, 4096), 256, 0, ctx->stream>>>(labels, n, k, counts, bad);
   LAUNCH_CHECK(ctx);
   return ANCKA_OK;
 }

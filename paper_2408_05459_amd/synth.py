@@ -76,11 +76,15 @@ class RunParams:
 
 
 def round_to_bf16(a: np.ndarray) -> np.ndarray:
-    """Round float32 values to the nearest bfloat16 (ties to even); returns float32."""
-    a = np.ascontiguousarray(a, dtype=np.float32)
-    b = a.view(np.uint32).astype(np.uint64)
-    r = (b + 0x7FFF + ((b >> 16) & 1)) >> 16
-    return (r.astype(np.uint32) << 16).view(np.float32).reshape(a.shape)
+    """Round finite float32 values to the nearest bfloat16 (ties to even); returns float32.
+    (For finite inputs the 32-bit sum below cannot overflow.)"""
+    a = np.array(a, dtype=np.float32, copy=True, order="C")
+    b = a.view(np.uint32)
+    lsb = (b >> np.uint32(16)) & np.uint32(1)
+    b += np.uint32(0x7FFF)
+    b += lsb
+    b &= np.uint32(0xFFFF0000)
+    return a
 
 
 def planted_labels(n: int, k: int, rng: np.random.Generator) -> np.ndarray:
@@ -149,34 +153,47 @@ def chung_lu_weights(n: int, mean: float, exponent: float, rng) -> np.ndarray:
     return theta * (mean / theta.mean())
 
 
+def _draw_proportional(count: int, nodes: np.ndarray, weights: np.ndarray, rng) -> np.ndarray:
+    """`count` i.i.d. draws from `nodes` with probability proportional to `weights`, in random
+    order (multinomial counts per node, expanded and shuffled)."""
+    if count == 0:
+        return np.empty(0, dtype=np.int64)
+    p = weights / weights.sum()
+    p[-1] = max(0.0, 1.0 - p[:-1].sum())
+    c = rng.multinomial(count, p)
+    out = np.repeat(nodes.astype(np.int64), c)
+    rng.shuffle(out)
+    return out
+
+
 def chung_lu_sbm(labels: np.ndarray, k: int, mean: float, exponent: float, intra: float,
                  rng: np.random.Generator):
     """Undirected planted-partition Chung-Lu graph, returned as a symmetric CSR."""
     n = labels.shape[0]
     theta = chung_lu_weights(n, mean, exponent, rng)
     order, csize, start = _cluster_index(labels, k)
-    cs_all = np.cumsum(theta)
-    total = cs_all[-1]
-    th_sorted = theta[order]
-    cs_cl = np.concatenate([[0.0], np.cumsum(th_sorted)])
     E = int(round(n * mean / 2.0))
+    allnodes = np.arange(n, dtype=np.int64)
 
-    u = np.searchsorted(cs_all, rng.random(E) * total, side="right")
-    u = np.minimum(u, n - 1)
+    u = _draw_proportional(E, allnodes, theta, rng)
     lu = labels[u]
     inside = rng.random(E) < intra
     v = np.empty(E, dtype=np.int64)
-    ci = lu[inside]
-    lo = cs_cl[start[ci]]
-    hi = cs_cl[start[ci + 1]]
-    tgt = lo + rng.random(ci.shape[0]) * (hi - lo)
-    pos = np.searchsorted(cs_cl, tgt, side="right") - 1
-    pos = np.clip(pos, start[ci], start[ci + 1] - 1)
-    v[inside] = order[pos]
+    # intra-cluster partner: proportional to theta inside u's cluster
+    sel = np.nonzero(inside)[0]
+    grp = np.argsort(lu[sel], kind="stable")
+    sel = sel[grp]
+    cnt = np.bincount(lu[sel], minlength=k)
+    off = 0
+    for c in range(k):
+        members = order[start[c]:start[c + 1]]
+        v[sel[off:off + cnt[c]]] = _draw_proportional(int(cnt[c]), members, theta[members], rng)
+        off += cnt[c]
+    # inter-cluster partner: proportional to theta over all nodes, redrawn while it falls in
+    # u's own cluster (rejection)
     todo = np.nonzero(~inside)[0]
     while todo.shape[0] > 0:
-        cand = np.searchsorted(cs_all, rng.random(todo.shape[0]) * total, side="right")
-        cand = np.minimum(cand, n - 1)
+        cand = _draw_proportional(todo.shape[0], allnodes, theta, rng)
         ok = labels[cand] != lu[todo]
         v[todo[ok]] = cand[ok]
         todo = todo[~ok]
@@ -204,14 +221,15 @@ def gmm_attributes(labels: np.ndarray, centres: np.ndarray, rng, out_dtype: str)
     n = labels.shape[0]
     d = centres.shape[1]
     X = np.empty((n, d), dtype=np.float32)
-    blk = 1 << 18
+    cen = centres.astype(np.float32)
+    blk = 1 << 16
     for s in range(0, n, blk):
         e = min(n, s + blk)
-        noise = rng.standard_normal((e - s, d), dtype=np.float32)
-        X[s:e] = centres[labels[s:e]].astype(np.float32) + noise
-    if out_dtype == "bf16":
-        X = round_to_bf16(X)
-    elif out_dtype == "f64":
+        rng.standard_normal((e - s, d), dtype=np.float32, out=X[s:e])
+        X[s:e] += cen[labels[s:e]]
+        if out_dtype == "bf16":
+            X[s:e] = round_to_bf16(X[s:e])
+    if out_dtype == "f64":
         X = X.astype(np.float64)
     return X
 

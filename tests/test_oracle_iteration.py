@@ -56,7 +56,11 @@ def symmetric_case_operator(kind, seed=0):
         assert (deg > 0).all()
         m = sizes.shape[0]
     else:
-        ptr, idx = synth.chung_lu_sbm(labels, k + 1, 12.0, 2.5, 0.9, rng)
+        # first seeded draw without an isolated node (the similarity argument needs D > 0)
+        for s in range(seed, seed + 100):
+            ptr, idx = synth.chung_lu_sbm(labels, k + 1, 12.0, 2.5, 0.9, np.random.default_rng(s))
+            if (np.diff(ptr) > 0).all():
+                break
         assert (np.diff(ptr) > 0).all()
         m = 0
     X = rng.standard_normal((n, 3))

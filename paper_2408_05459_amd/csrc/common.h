@@ -57,6 +57,7 @@ struct ancka_op {
   double* beta = nullptr;
   int64_t* delta = nullptr;
   double* dk = nullptr;
+  int32_t* rorder = nullptr;          // node rows in processing order (coarse attribute cells), nullable
   int64_t nnz_knn = 0, nnz_topo = 0, nnz_edge = 0;
   std::vector<void*> owned;
 };
@@ -109,6 +110,10 @@ ancka_status unique_sorted(ancka_ctx* ctx, const uint64_t* keys, const uint64_t*
 ancka_status csr_ptr_from_sorted(ancka_ctx* ctx, const uint64_t* keys, int64_t count, int col_bits,
                                  int64_t rows, int64_t* row_ptr);
 ancka_status fill_zero(ancka_ctx* ctx, void* p, size_t bytes);
+
+// Rows of X (n x d, xdtype) ordered by coarse cell (most similar of 64 evenly spaced pivot
+// rows), then by norm: order[p] = row at position p (knn.hip).
+ancka_status cell_order(ancka_ctx* ctx, const void* X, int xdtype, int64_t n, int64_t d, int64_t ldx, int32_t* order);
 
 // ------------------------------------------------------------------------------------------
 // sparse products (spmm.hip)

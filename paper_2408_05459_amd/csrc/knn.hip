@@ -420,7 +420,14 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
 // cell of each row: the most similar of NPIV pivot rows (dot with the pivot scaled by its inverse
 // norm; ties to the smaller pivot).  Pivots are held in LDS as bf16; a thread owns a row and
 // sweeps it 8 elements at a time against every pivot.
-__global__ __launch_bounds__(256) void cell_assign_kernel(const uint16_t* __restrict__ X, int64_t n, int64_t d,
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+
+template <typename TX>
+__global__ __launch_bounds__(256) void cell_assign_kernel(const TX* __restrict__ X, int64_t n, int64_t d,
                                                           int64_t ldx, const float* __restrict__ invn,
                                                           const int64_t* __restrict__ piv, uint64_t* __restrict__ keys,
                                                           const float* __restrict__ nrm, uint64_t* __restrict__ vals) {
@@ -430,7 +437,7 @@ __global__ __launch_bounds__(256) void cell_assign_kernel(const uint16_t* __rest
   float* pinv = (float*)(P + NPIV * dp);    // [NPIV]
   for (int e = threadIdx.x; e < NPIV * dp; e += 256) {
     const int p = e / dp, c = e % dp;
-    P[e] = (c < d) ? X[piv[p] * ldx + c] : (uint16_t)0;
+    P[e] = (c < d) ? f32_to_bf16_rne((float)load_as_double<TX>(X, piv[p] * ldx + c)) : (uint16_t)0;
   }
   if (threadIdx.x < NPIV) pinv[threadIdx.x] = invn[piv[threadIdx.x]];
   __syncthreads();
@@ -439,11 +446,11 @@ __global__ __launch_bounds__(256) void cell_assign_kernel(const uint16_t* __rest
   float acc[NPIV];
 #pragma unroll
   for (int p = 0; p < NPIV; p++) acc[p] = 0.0f;
-  const uint16_t* xr = X + i * ldx;
+  const TX* xr = X + i * ldx;
   for (int c0 = 0; c0 < dp; c0 += 8) {
     float xv[8];
 #pragma unroll
-    for (int u = 0; u < 8; u++) xv[u] = (c0 + u < d) ? bf16_to_f32(xr[c0 + u]) : 0.0f;
+    for (int u = 0; u < 8; u++) xv[u] = (c0 + u < d) ? (float)load_as_double<TX>(xr, c0 + u) : 0.0f;
 #pragma unroll
     for (int p = 0; p < NPIV; p++) {
       const uint4 pv = *(const uint4*)(P + p * dp + c0);
@@ -517,6 +524,11 @@ __global__ void wg_start_kernel(const uint64_t* __restrict__ keys, int64_t n, in
     else hi = mid;
   }
   start[b] = (int32_t)(lo / BT_C);
+}
+
+__global__ void u64_to_i32_kernel(const uint64_t* __restrict__ a, int64_t n, int32_t* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (int32_t)a[i];
 }
 
 // ---- FP64 rescoring of the candidate lists + certificate --------------------------------------
@@ -809,12 +821,12 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
       const size_t csm = (size_t)NPIV * ((d + 7) / 8 * 8) * 2 + NPIV * 4;
       static bool cattr = false;
       if (!cattr) {
-        HIP_TRY(ctx, hipFuncSetAttribute((const void*)cell_assign_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         160 * 1024));
+        HIP_TRY(ctx, hipFuncSetAttribute((const void*)cell_assign_kernel<uint16_t>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         cattr = true;
       }
-      cell_assign_kernel<<<(unsigned)cdiv(n, 256), 256, csm, ctx->stream>>>((const uint16_t*)(const void*)X, n, d, ldx,
-                                                                            invn, piv, keys, nrm, order);
+      cell_assign_kernel<uint16_t><<<(unsigned)cdiv(n, 256), 256, csm, ctx->stream>>>(
+          (const uint16_t*)(const void*)X, n, d, ldx, invn, piv, keys, nrm, order);
       LAUNCH_CHECK(ctx);
       ST_TRY(radix_sort_u64(ctx, keys, order, n, 40));
       gather_sorted_kernel<<<(unsigned)cdiv(n, 4), 256, 0, ctx->stream>>>((const uint16_t*)(const void*)X, n, d, ldx,
@@ -845,6 +857,41 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
   return ANCKA_OK;
 }
 
+template <typename TX>
+ancka_status cell_order_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_t ldx, int32_t* order_out) {
+  double* sq = nullptr;
+  float *invn = nullptr, *nrm = nullptr;
+  unsigned long long* zc = nullptr;
+  uint64_t *keys = nullptr, *vals = nullptr;
+  int64_t* piv = nullptr;
+  ST_TRY(ws_get_t(ctx, "co_sq", (size_t)n, &sq));
+  ST_TRY(ws_get_t(ctx, "co_invn", (size_t)n, &invn));
+  ST_TRY(ws_get_t(ctx, "co_nrm", (size_t)n, &nrm));
+  ST_TRY(ws_get_t(ctx, "co_zero", 2, &zc));
+  ST_TRY(ws_get_t(ctx, "co_keys", (size_t)n, &keys));
+  ST_TRY(ws_get_t(ctx, "co_vals", (size_t)n, &vals));
+  ST_TRY(ws_get_t(ctx, "co_piv", NPIV, &piv));
+  knn_prologue_kernel<TX><<<(unsigned)cdiv(n, 4), 256, 0, ctx->stream>>>(X, n, d, ldx, sq, invn, nrm, nullptr, 0, zc);
+  LAUNCH_CHECK(ctx);
+  int64_t hp[NPIV];
+  for (int p = 0; p < NPIV; p++) hp[p] = (int64_t)((double)p * (double)n / NPIV);
+  HIP_TRY(ctx, hipMemcpyAsync(piv, hp, sizeof(hp), hipMemcpyHostToDevice, ctx->stream));
+  const size_t csm = (size_t)NPIV * ((d + 7) / 8 * 8) * 2 + NPIV * 4;
+  if (csm > 160 * 1024) return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "cell order: d too large");
+  static bool cattr = false;
+  if (!cattr) {
+    HIP_TRY(ctx, hipFuncSetAttribute((const void*)cell_assign_kernel<TX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     160 * 1024));
+    cattr = true;
+  }
+  cell_assign_kernel<TX><<<(unsigned)cdiv(n, 256), 256, csm, ctx->stream>>>(X, n, d, ldx, invn, piv, keys, nrm, vals);
+  LAUNCH_CHECK(ctx);
+  ST_TRY(radix_sort_u64(ctx, keys, vals, n, 40));
+  u64_to_i32_kernel<<<(unsigned)cdiv(n, 256), 256, 0, ctx->stream>>>(vals, n, order_out);
+  LAUNCH_CHECK(ctx);
+  return ANCKA_OK;
+}
+
 }  // namespace
 
 extern "C" ancka_status ancka_knn(ancka_ctx* ctx, const void* X, int32_t xdtype, int64_t n, int64_t d, int64_t ldx,
@@ -864,5 +911,14 @@ extern "C" ancka_status ancka_knn(ancka_ctx* ctx, const void* X, int32_t xdtype,
     case ANCKA_F32: return knn_typed<float>(ctx, (const float*)X, n, d, ldx, K, mode, nbr_idx, nbr_sim, stats);
     case ANCKA_BF16: return knn_typed<uint16_t>(ctx, (const uint16_t*)X, n, d, ldx, K, mode, nbr_idx, nbr_sim, stats);
     default: return set_err(ctx, ANCKA_ERR_INVALID_ARG, "ancka_knn: unknown dtype %d", xdtype);
+  }
+}
+
+ancka_status cell_order(ancka_ctx* ctx, const void* X, int xdtype, int64_t n, int64_t d, int64_t ldx, int32_t* order) {
+  switch (xdtype) {
+    case ANCKA_F64: return cell_order_typed<double>(ctx, (const double*)X, n, d, ldx, order);
+    case ANCKA_F32: return cell_order_typed<float>(ctx, (const float*)X, n, d, ldx, order);
+    case ANCKA_BF16: return cell_order_typed<uint16_t>(ctx, (const uint16_t*)X, n, d, ldx, order);
+    default: return set_err(ctx, ANCKA_ERR_INVALID_ARG, "cell order: unknown dtype %d", xdtype);
   }
 }

@@ -336,6 +336,14 @@ ancka_status build_typed(ancka_ctx* ctx, const ancka_network* net, const int32_t
   knn_values_kernel<T><<<nb256(n), 256, 0, ctx->stream>>>(op->kptr, akv, op->dk, op->beta, n, (T*)op->kval);
   LAUNCH_CHECK(ctx);
 
+  // processing order of node rows for the sparse products: rows of one coarse attribute cell
+  // are handled together, so the rows they gather (mostly in the same cell) stay in cache
+  if (net->X && net->d >= 1 && net->ldx >= net->d) {
+    ST_TRY(op_alloc(ctx, op, sizeof(int32_t) * n, &p));
+    op->rorder = (int32_t*)p;
+    ST_TRY(cell_order(ctx, net->X, net->xdtype, n, net->d, net->ldx, op->rorder));
+  }
+
   int hbad = 0;
   HIP_TRY(ctx, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

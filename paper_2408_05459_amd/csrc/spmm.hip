@@ -81,6 +81,7 @@ struct SpmmArgs {
   const int32_t* labels;   // EPI_MHC: label of each row; EPI_INIT: centre index of each row or -1
   const int32_t* counts;   // EPI_MHC: cluster sizes
   T b;
+  const int32_t* rorder;   // nullable: output row handled by slot w is rorder[w]
 };
 
 template <typename T, int LPR>
@@ -140,8 +141,9 @@ __global__ __launch_bounds__(256) void spmm_kernel(const SpmmArgs<T> A) {
   constexpr int W = V16<T>::W;
   constexpr int RPB = 256 / LPR;
   const int sub = threadIdx.x % LPR;
-  const int64_t r = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR;
-  if (r >= A.rows) return;   // whole lane groups exit together
+  const int64_t w = (int64_t)blockIdx.x * RPB + threadIdx.x / LPR;
+  if (w >= A.rows) return;   // whole lane groups exit together
+  const int64_t r = A.rorder ? (int64_t)A.rorder[w] : w;
   const int coff = sub * W;
   const bool col_ok = coff < A.cols;
   T acc[W];
@@ -236,6 +238,7 @@ SpmmArgs<T> blank(int64_t rows, T* out, int64_t ld, int cols) {
   A.labels = nullptr;
   A.counts = nullptr;
   A.b = (T)0;
+  A.rorder = nullptr;
   return A;
 }
 
@@ -259,6 +262,7 @@ ancka_status apply_typed(ancka_ctx* ctx, const ancka_op* op, const T* Q, T* Z, i
   SpmmArgs<T> S = blank<T>(n, Z, ld, cols);
   S.segs = op->kind == ANCKA_HYPERGRAPH ? 1 : op->L;
   S.tptr = op->tptr;
+  S.rorder = op->rorder;
   S.tidx = op->tidx;
   S.tscale = (const T*)op->tscale;
   S.tsrc = topo_src;
@@ -292,6 +296,7 @@ ancka_status init_typed(ancka_ctx* ctx, const ancka_op* op, const T* Pin, T* Pou
     ST_TRY(launch_spmm<T>(ctx, S1));
     SpmmArgs<T> S2 = blank<T>(n, Pout, ld, cols);
     S2.tptr = op->tptr;
+    S2.rorder = op->rorder;
     S2.tidx = op->tidx;
     S2.tsrc = E;
     S2.a = a;
@@ -303,6 +308,7 @@ ancka_status init_typed(ancka_ctx* ctx, const ancka_op* op, const T* Pin, T* Pou
   SpmmArgs<T> S = blank<T>(n, Pout, ld, cols);
   S.segs = op->L;
   S.tptr = op->tptr;
+  S.rorder = op->rorder;
   S.tidx = op->tidx;
   S.tcol = (const T*)op->tcol;      // 1/(L_j deg_l(j)) of the source node in layer l
   S.tsrc = Pin;
@@ -356,6 +362,7 @@ ancka_status op_apply_features(ancka_ctx* ctx, const ancka_op* op, const float* 
       ST_TRY(launch_spmm<float>(ctx, S1));
       SpmmArgs<float> S2 = blank<float>(op->n, dst, ld, w);
       S2.tptr = op->tptr;
+      S2.rorder = op->rorder;
       S2.tidx = op->tidx;
       S2.tscale = (const float*)op->tcol;   // 1/delta(u) per node
       S2.tsrc = E;
@@ -368,6 +375,7 @@ ancka_status op_apply_features(ancka_ctx* ctx, const ancka_op* op, const float* 
       SpmmArgs<float> S = blank<float>(op->n, dst, ld, w);
       S.segs = op->L;
       S.tptr = op->tptr;
+      S.rorder = op->rorder;
       S.tidx = op->tidx;
       S.tscale = (const float*)op->tcol;    // 1/(L_i deg_l(i)) per segment
       S.tsrc = src;

@@ -1,16 +1,46 @@
 """FP64 oracle of the learned warm start (TEST INFRASTRUCTURE ONLY).
 
-The paper has no learned component; this follows the warm-start design of this
+The paper has no learned component.  This follows the warm-start design of this
 project: a three-layer perceptron d -> h1 -> h2 -> k applied to the one-hop
 aggregated, row-normalised attributes U = (X^ + P_N X^) / 2, trained with the
-mean squared error against target blocks.  Plain numpy FP64; the backward pass
-is the analytic chain rule.
+mean squared error against target blocks built from the plain method's own
+eigenblocks.  Plain numpy FP64; the backward pass is the analytic chain rule.
+
+Precision model.  The network's products take BF16 operands with wide
+accumulation: the input U, the weights and the hidden activations are rounded
+to BF16 (FP32 value, then round-to-nearest-even to 8 significant bits), biases
+stay FP32.  Passing ``rnd=round_bf16`` reproduces these rounding points in
+FP64 arithmetic; ``rnd=None`` is the exact real-valued network.
+
+Parity status:
+  mlp_features             pinned (hand-computed walk average)
+  mlp_forward/backward     pinned (central finite differences; rounded mode
+                           equals exact mode on BF16-representable data)
+  round_bf16               pinned (library BF16 conversion)
+  adam_step                pinned (closed forms of the first step and of a
+                           constant gradient)
+  warm_target              pinned (planted rotation and centre permutation)
 """
 from __future__ import annotations
 
 import numpy as np
+from scipy.optimize import linear_sum_assignment
 
-__all__ = ["mlp_features", "mlp_forward", "mlp_loss", "mlp_backward"]
+__all__ = ["mlp_features", "mlp_forward", "mlp_loss", "mlp_backward", "round_bf16", "adam_step",
+           "warm_target"]
+
+
+def round_bf16(x):
+    """Value of x after FP32 rounding then round-to-nearest-even to BF16 (8 significant
+    bits, FP32 exponent range).  Returns float64."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float64).astype(np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _ident(a):
+    return np.asarray(a, dtype=np.float64)
 
 
 def mlp_features(Xh, P_N):
@@ -20,14 +50,17 @@ def mlp_features(Xh, P_N):
     return 0.5 * (Xh + P_N @ Xh)
 
 
-def mlp_forward(U, W1, b1, W2, b2, W3, b3):
-    """Z^ = relu(relu(U W1 + b1) W2 + b2) W3 + b3; returns (Z^, cache)."""
-    A1 = np.asarray(U, np.float64) @ W1 + b1
-    H1 = np.maximum(A1, 0.0)
-    A2 = H1 @ W2 + b2
-    H2 = np.maximum(A2, 0.0)
-    Z = H2 @ W3 + b3
-    return Z, (np.asarray(U, np.float64), A1, H1, A2, H2)
+def mlp_forward(U, W1, b1, W2, b2, W3, b3, rnd=None):
+    """Z^ = relu(relu(U W1 + b1) W2 + b2) W3 + b3, weights laid out (in, out).
+
+    With rnd, U, the weights and both hidden activations pass through rnd before they
+    enter a product.  Returns (Z^, cache) where cache holds the product inputs."""
+    r = rnd or _ident
+    U0 = r(U)
+    H1 = r(np.maximum(U0 @ r(W1) + b1, 0.0))
+    H2 = r(np.maximum(H1 @ r(W2) + b2, 0.0))
+    Z = H2 @ r(W3) + b3
+    return Z, (U0, H1, H2)
 
 
 def mlp_loss(Z, T):
@@ -36,17 +69,68 @@ def mlp_loss(Z, T):
     return float((D * D).sum() / Z.shape[0])
 
 
-def mlp_backward(Z, T, cache, W1, W2, W3):
-    """Gradients of mlp_loss with respect to (W1, b1, W2, b2, W3, b3)."""
-    U, A1, H1, A2, H2 = cache
+def mlp_backward(Z, T, cache, W1, W2, W3, rnd=None):
+    """Gradients of mlp_loss with respect to (W1, b1, W2, b2, W3, b3).
+
+    The relu derivative is taken where the stored activation is positive.  With rnd, the
+    output gradient and both hidden-layer gradients pass through rnd before they enter a
+    product (the same rounding points as the forward pass)."""
+    r = rnd or _ident
+    U0, H1, H2 = cache
     n = Z.shape[0]
-    dZ = 2.0 * (np.asarray(Z, np.float64) - T) / n
-    dW3 = H2.T @ dZ
-    db3 = dZ.sum(axis=0)
-    dA2 = (dZ @ W3.T) * (A2 > 0)
-    dW2 = H1.T @ dA2
-    db2 = dA2.sum(axis=0)
-    dA1 = (dA2 @ W2.T) * (A1 > 0)
-    dW1 = U.T @ dA1
-    db1 = dA1.sum(axis=0)
+    G3 = r(2.0 * (np.asarray(Z, np.float64) - T) / n)
+    dW3 = H2.T @ G3
+    db3 = G3.sum(axis=0)
+    G2 = r((G3 @ r(W3).T) * (H2 > 0))
+    dW2 = H1.T @ G2
+    db2 = G2.sum(axis=0)
+    G1 = r((G2 @ r(W2).T) * (H1 > 0))
+    dW1 = U0.T @ G1
+    db1 = G1.sum(axis=0)
     return dW1, db1, dW2, db2, dW3, db3
+
+
+def adam_step(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One step of Adam (Kingma and Ba, 2015, Algorithm 1) at step count t >= 1: moment
+    updates, bias correction by 1 - beta^t, then p - lr m^ / (sqrt(v^) + eps).
+    Returns (p, m, v)."""
+    g = np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** t)
+    vh = v / (1.0 - beta2 ** t)
+    return np.asarray(p, np.float64) - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def warm_target(Q, R, labels, Xh, centres):
+    """Training target of the warm start from one run of the plain method.
+
+    Q: n x (k+1) orthonormal block of the orthogonal iteration; R: k x k rotation of its
+    last Discretize (Alg. 5); labels: that Discretize's labels; Xh: row-normalised
+    attributes; centres: the k mixture centres shared by every graph of the family.
+    The block Q[:, 1:] is row-normalised (zero rows stay zero) and rotated, Y = Q~ R,
+    so column c is the soft indicator of cluster c.  Column c is then moved to the
+    centre that cluster c matches: assignment maximising the total cosine between the
+    clusters' mean attribute vectors and the centres (Hungarian method).
+    Returns (T, colmap) with T[:, colmap[c]] = Y[:, c]."""
+    Q = np.asarray(Q, np.float64)
+    k = R.shape[0]
+    B = Q[:, 1:k + 1]
+    nr = np.sqrt((B * B).sum(axis=1))
+    Qt = np.divide(B, nr[:, None], out=np.zeros_like(B), where=nr[:, None] > 0)
+    Y = Qt @ np.asarray(R, np.float64)
+    C = np.asarray(centres, np.float64)
+    C = C / np.linalg.norm(C, axis=1, keepdims=True)
+    cos = np.zeros((k, k))
+    for c in range(k):
+        rows = np.flatnonzero(labels == c)
+        if rows.size == 0:
+            continue
+        mu = np.asarray(Xh, np.float64)[rows].mean(axis=0)
+        nm = np.linalg.norm(mu)
+        if nm > 0:
+            cos[c] = C @ (mu / nm)
+    _, colmap = linear_sum_assignment(-cos)
+    T = np.zeros_like(Y)
+    T[:, colmap] = Y
+    return T, colmap

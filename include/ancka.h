@@ -134,7 +134,7 @@ ancka_params ancka_default_params(void);
 /* Number of compute units / XCD count seen by the context (host). */
 ancka_status ancka_device_info(ancka_ctx* ctx, int32_t* num_cu, int32_t* warp_size);
 
-/* ---- KNN graph (Sec. 3.1 KNN augmentation; Alg. 6 lines 1-5) ------------------------------
+/* ---- KNN graph (Sec. 3.1 KNN augmentation; Alg. 6, neighbour search) ------------------------------
  * For every row i of X (n x d, leading dimension ldx, element type xdtype), the K rows j != i
  * with the largest cosine similarity f(i, j) = x_i.x_j / (|x_i| |x_j|), ordered by
  * (f desc, j asc).  A zero row is never a candidate; its own list is idx -1, sim 0.  Rows
@@ -176,7 +176,7 @@ ancka_status ancka_op_info(ancka_ctx* ctx, const ancka_op* op, double* beta, int
 ancka_status ancka_apply_p(ancka_ctx* ctx, const ancka_op* op, const void* Q, void* Z, int32_t cols,
                            int64_t ld);
 
-/* ---- greedy initial BCM (Alg. 3; Alg. 4 lines 3-11; Eqs. pi_c_t, argmaxlabel) ---------------
+/* ---- greedy initial BCM (Alg. 3; Alg. 4, greedy start; Eqs. pi_c_t, argmaxlabel) ---------------
  * V_c = the k nodes of largest degree (ties: smaller index) listed by index; T_i steps of
  * Pi <- (1-alpha) Pi P_N + alpha Z_0 on the topology walk only; label of v_j = argmax_l
  * Pi[l, j], smallest l on ties.  labels: int32 n (device).
@@ -184,7 +184,7 @@ ancka_status ancka_apply_p(ancka_ctx* ctx, const ancka_op* op, const void* Q, vo
 ancka_status ancka_init_bcm(ancka_ctx* ctx, const ancka_op* op, int32_t k, double alpha, int32_t T_i,
                             int32_t* labels);
 
-/* ---- starting block (Alg. 4 lines 12-13) ---------------------------------------------------
+/* ---- starting block (Alg. 4, starting block) ---------------------------------------------------
  * Q (n x (k+1), leading dimension ldq, op's dtype) = orthonormalised [1/sqrt(n) 1 | h(Y)]
  * with h(Y) of Eq. (norm-y) built from `labels`, or [1/sqrt(n) 1 | Zwarm] when `labels` is
  * NULL and `zwarm` (float n x k, leading dimension k) is given.  The block is orthonormalised
@@ -233,36 +233,81 @@ ancka_status ancka_mhc(ancka_ctx* ctx, const ancka_op* op, const int32_t* labels
 ancka_status ancka_cluster(ancka_ctx* ctx, const ancka_network* net, const ancka_params* params,
                            const float* zwarm, int32_t* labels, ancka_report* rep);
 
-/* ---- learned warm start (not part of the paper: a small MLP d -> h1 -> h2 -> k predicting the
- * rotated eigenblock from one-hop aggregated attributes; BF16 weights, FP32 accumulation) ---- */
+/* The same method from an operator built by ancka_build_operator (Alg. 4 from the greedy start
+ * on): callers that already hold the operator, e.g. to aggregate the warm-start features with
+ * its walk, skip the second KNN search.  params->q_dtype must equal the operator's dtype and
+ * params->K is not used.  The report's KNN and operator phases stay zero.  Synchronises.
+ * Errors: as ancka_cluster. */
+ancka_status ancka_cluster_op(ancka_ctx* ctx, const ancka_op* op, const ancka_params* params,
+                              const float* zwarm, int32_t* labels, ancka_report* rep);
+
+/* ---- learned warm start (not part of the paper) -------------------------------------------
+ * A three-layer perceptron d_in -> h1 -> h2 -> k that predicts, for every node, its row of the
+ * plain method's rotated eigenblock from its one-hop aggregated attributes; its argmax rows and
+ * the block [1/sqrt(n) | Zhat] replace the greedy start of Alg. 4 (see ancka_cluster's zwarm).
+ * Every matrix product takes BF16 operands (FP32 values rounded to nearest even) and
+ * accumulates in FP32: the input U, the weights and both hidden activations are rounded, the
+ * biases, the FP32 master weights and the Adam state are not.  Weights are laid out (in, out),
+ * row-major; H1 = relu(U W1 + b1), H2 = relu(H1 W2 + b2), Zhat = H2 W3 + b3.
+ * A model belongs to the device of the context that created it; calls on one model must not
+ * overlap. */
 typedef struct ancka_ws ancka_ws;
 
-/* Create a model with weights drawn from a seeded uniform(-1/sqrt(fan_in), 1/sqrt(fan_in))
- * (SplitMix64 stream of `seed`).  Errors: INVALID_ARG unless 1 <= d_in <= 4096,
- * 16 <= h1, h2 <= 1024 (multiples of 16), 1 <= k <= 64. */
+/* Create a model: weights uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) drawn in order W1, W2, W3
+ * from the SplitMix64 stream of `seed` (53-bit uniforms), biases zero, Adam state zero.
+ * Errors: INVALID_ARG unless 1 <= d_in <= 4096, 16 <= h1, h2 <= 1024 (multiples of 16) and
+ * 1 <= k <= 64; OOM. */
 ancka_status ancka_ws_create(ancka_ctx* ctx, int32_t d_in, int32_t h1, int32_t h2, int32_t k,
                              uint64_t seed, ancka_ws** out);
 void ancka_ws_destroy(ancka_ws* ws);
-/* U = (X^ + P_N X^) / 2 for every node, as float n x d_in (device, caller-owned). */
+
+/* Input features U = (X^ + P_N X^) / 2 of every node of the operator's network, X^ the rows of
+ * X scaled to unit L2 norm (zero rows stay zero) and P_N the operator's topology walk (hypergraph
+ * P_V P_E, graph D^-1 A, multiplex average over the layers where the node has edges; an isolated
+ * node keeps U = X^ / 2).  X: device n x d, leading dimension ldx, xdtype F64 / F32 / BF16.
+ * U: device float n x ldu (caller-owned; columns d..ldu-1 are left untouched).
+ * Errors: INVALID_ARG unless d >= 1, ldx >= d, ldu >= d and ldu % 4 == 0. */
 ancka_status ancka_ws_features(ancka_ctx* ctx, const ancka_op* op, const void* X, int32_t xdtype,
-                               int64_t d, int64_t ldx, float* U);
-/* Zhat = MLP(U) (float n x k, device, caller-owned).  keep_acts = 1 keeps the activations
- * needed by ancka_ws_backward (inside ws, sized for n). */
-ancka_status ancka_ws_forward(ancka_ctx* ctx, ancka_ws* ws, const float* U, int64_t n, float* zhat,
-                              int32_t keep_acts);
-/* Mean squared error against T (float n x k) and the gradients of the last forward with
- * keep_acts = 1, stored inside ws.  loss: host, nullable (synchronises when given). */
+                               int64_t d, int64_t ldx, float* U, int64_t ldu);
+
+/* Zhat = MLP(U).  U: device float n x ldu (the first d_in columns are read); zhat: device float
+ * n x k, contiguous.  keep_acts = 1 keeps the rounded input and activations inside ws for
+ * ancka_ws_backward (workspace grows to n rows).  Errors: INVALID_ARG unless n >= 1, ldu >= d_in. */
+ancka_status ancka_ws_forward(ancka_ctx* ctx, ancka_ws* ws, const float* U, int64_t n, int64_t ldu,
+                              float* zhat, int32_t keep_acts);
+
+/* Mean squared error loss = (1/n) sum_i ||zhat_i - T_i||^2 of the last forward with
+ * keep_acts = 1 (same n), and its gradients with respect to every parameter, stored inside ws
+ * (read them with ancka_ws_get_params(which = 1)).  The output gradient 2 (zhat - T) / n and
+ * both hidden-layer gradients are rounded to BF16 before they enter a product; the relu
+ * derivative is 1 where the stored activation is positive.  zhat, T: device float n x k.
+ * loss: host, nullable (synchronises when given).
+ * Errors: INVALID_ARG if no activations of n rows are kept. */
 ancka_status ancka_ws_backward(ancka_ctx* ctx, ancka_ws* ws, const float* zhat, const float* T,
                                int64_t n, double* loss);
-/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 master weights, then the BF16
- * copies used by forward are refreshed. */
+
+/* One Adam step (Kingma and Ba 2015: beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * FP32 master weights and biases with the stored gradients; the BF16 copies used by the
+ * products are refreshed.  Errors: INVALID_ARG unless lr > 0. */
 ancka_status ancka_ws_step(ancka_ctx* ctx, ancka_ws* ws, double lr);
-/* Host copies of the parameters / gradients, packed W1 (d_in x h1), b1, W2 (h1 x h2), b2,
- * W3 (h2 x k), b3 as float.  which: 0 BF16-rounded weights used by forward, 1 gradients,
- * 2 FP32 master weights.  ancka_ws_set_params writes the master weights and refreshes the
- * BF16 copies.  count: number of floats of the packed vector (host, out). */
+
+/* Host copies of the parameters, packed W1 (d_in x h1), b1, W2 (h1 x h2), b2, W3 (h2 x k), b3 as
+ * float.  which: 0 the values the forward pass uses (BF16-rounded weights, FP32 biases),
+ * 1 the gradients of the last backward, 2 the FP32 master weights.  host nullable (then only
+ * count is written); count: host, out, number of floats.  Synchronises.
+ * ancka_ws_set_params writes the master weights from the same packing, refreshes the BF16
+ * copies and clears the Adam state and step count. */
 ancka_status ancka_ws_get_params(ancka_ctx* ctx, ancka_ws* ws, int32_t which, float* host, int64_t* count);
 ancka_status ancka_ws_set_params(ancka_ctx* ctx, ancka_ws* ws, const float* host);
+
+/* Training target from one run of the plain method: T[:, colmap[c]] = (Q~ R)[:, c], where Q~ are
+ * the rows of the n x k block Q scaled to unit L2 norm (zero rows stay zero) and R the rotation
+ * of its last Discretize (ancka_discretize's R, host double k x k row-major).  Q: device, qdtype
+ * F32 / F64, leading dimension ldq (a pointer to column 1 of the orthogonal-iteration block);
+ * colmap: host int32 k, a permutation of 0..k-1 (the cluster-to-centre assignment); T: device
+ * float n x k.  Errors: INVALID_ARG unless 1 <= k <= 64, ldq >= k and colmap is a permutation. */
+ancka_status ancka_ws_target(ancka_ctx* ctx, const void* Q, int32_t qdtype, int64_t n, int32_t k,
+                             int64_t ldq, const double* R, const int32_t* colmap, float* T);
 
 #ifdef __cplusplus
 }

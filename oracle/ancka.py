@@ -25,10 +25,10 @@ __all__ = [
 
 
 # --------------------------------------------------------------------------------------
-# Attribute prologue and KNN graph (Sec. 3.1; Alg. 6 lines 1-2)
+# Attribute prologue and KNN graph (Sec. 3.1; Alg. 6, normalisation step)
 
 def normalize_rows(X):
-    """x_i / ||x_i||_2; rows with zero norm stay zero and are flagged (Alg. 6, lines 1-2).
+    """x_i / ||x_i||_2; rows with zero norm stay zero and are flagged (Alg. 6, normalisation step).
 
     Reading: a zero attribute vector has no cosine similarity to anything, so it is never a
     neighbour candidate and has no neighbours (its beta_i is 0 by Eq. beta_i)."""
@@ -211,7 +211,7 @@ def build_operator(kind, n, ptrs, idxs, m, zero, nbr_idx, nbr_sim, beta, literal
                    literal_zero_rows=False):
     """Assemble P = (I - B) P_N + B P_K (Eq. p-mat-ancka) without multiplying it out.
 
-    P_K = D_K^-1 A_K (Alg. 6 lines 7-10).  Reading for a node whose row of P would be empty
+    P_K = D_K^-1 A_K (Alg. 6, graph construction).  Reading for a node whose row of P would be empty
     (beta_i = 0 and no topology edge): it gets a self loop P[i, i] = 1 so that P stays
     row-stochastic (switch off with ``literal_zero_rows``)."""
     top = topology_transition(kind, n, ptrs, idxs, m, literal_rw_mg)
@@ -257,10 +257,10 @@ def multi_hop_dense(op: Operator, alpha, gamma):
 
 
 # --------------------------------------------------------------------------------------
-# Greedy initialisation (Alg. 3 / Alg. 4 lines 3-11, Eqs. pi_c_t and argmaxlabel)
+# Greedy initialisation (Alg. 3 / Alg. 4, greedy start, Eqs. pi_c_t and argmaxlabel)
 
 def centres(delta, k):
-    """V_c: the k nodes of largest degree, listed by node index (Alg. 4 line 3).
+    """V_c: the k nodes of largest degree, listed by node index (Alg. 4, choice of the centres).
     Reading for degree ties: the smaller index ranks first."""
     delta = np.asarray(delta)
     order = np.lexsort((np.arange(delta.shape[0]), -delta))
@@ -302,7 +302,7 @@ def fill_vector(n, j):
 
 
 def initial_q(C, tol=1e-8):
-    """Orthonormal basis of the starting block (Alg. 4 lines 12-13).
+    """Orthonormal basis of the starting block (Alg. 4, starting block).
 
     Reading: [1/sqrt(n) 1 | h(Y0)] has rank k at most, because the all-ones vector is the
     sum of the cluster indicators; it is orthonormalised column by column (Gram-Schmidt,
@@ -409,7 +409,7 @@ def discretize(Qk, max_iter=30, tol=1e-12, colnorm="l1"):
 
 
 # --------------------------------------------------------------------------------------
-# Multi-hop conductance (Alg. 2 / Alg. 4 lines 19-21, Eq. mhc-comp-ancka)
+# Multi-hop conductance (Alg. 2 / Alg. 4, conductance evaluation, Eq. mhc-comp-ancka)
 
 def mhc(op: Operator, labels, k, alpha, gamma):
     """phi = 1 - (1/k) trace(Yh^T F^(gamma)) with F^(0) = alpha Yh and
@@ -445,8 +445,8 @@ def cluster(op: Operator, k, alpha=0.2, gamma=3, tau=5, T_i=25, T_a=1000, eps_q=
             disc_max_iter=30, Zwarm=None):
     """Alg. 4 from the initial BCM to the returned labels.
 
-    Readings: Phi(Y^(0)) is evaluated before the loop so that line 22 has something to
-    compare with; Eq. (tcond-2) is tested on the history [phi_0, phi_tau, phi_2tau, ...]
+    Readings: Phi(Y^(0)) is evaluated before the loop so that the first comparison
+    with the best labels so far has a value; Eq. (tcond-2) is tested on the history [phi_0, phi_tau, phi_2tau, ...]
     once three values exist; the norm of Eq. (tcond-1) is the Frobenius norm of the whole
     block; Discretize gets columns 2..k+1 of Q (the first, constant eigenvector is
     dropped, Sec. 4).  With ``Zwarm`` (n x k), the learned warm start replaces the greedy

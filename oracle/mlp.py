@@ -19,6 +19,7 @@ Parity status:
   round_bf16               pinned (library BF16 conversion)
   adam_step                pinned (closed forms of the first step and of a
                            constant gradient)
+  rotated_block, centre_map,
   warm_target              pinned (planted rotation and centre permutation)
 """
 from __future__ import annotations
@@ -27,7 +28,7 @@ import numpy as np
 from scipy.optimize import linear_sum_assignment
 
 __all__ = ["mlp_features", "mlp_forward", "mlp_loss", "mlp_backward", "round_bf16", "adam_step",
-           "warm_target"]
+           "rotated_block", "centre_map", "warm_target"]
 
 
 def round_bf16(x):
@@ -102,24 +103,22 @@ def adam_step(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return np.asarray(p, np.float64) - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def warm_target(Q, R, labels, Xh, centres):
-    """Training target of the warm start from one run of the plain method.
-
-    Q: n x (k+1) orthonormal block of the orthogonal iteration; R: k x k rotation of its
-    last Discretize (Alg. 5); labels: that Discretize's labels; Xh: row-normalised
-    attributes; centres: the k mixture centres shared by every graph of the family.
-    The block Q[:, 1:] is row-normalised (zero rows stay zero) and rotated, Y = Q~ R,
-    so column c is the soft indicator of cluster c.  Column c is then moved to the
-    centre that cluster c matches: assignment maximising the total cosine between the
-    clusters' mean attribute vectors and the centres (Hungarian method).
-    Returns (T, colmap) with T[:, colmap[c]] = Y[:, c]."""
-    Q = np.asarray(Q, np.float64)
-    k = R.shape[0]
-    B = Q[:, 1:k + 1]
+def rotated_block(Q, R):
+    """Y = Q~ R: the rows of the n x k block Q scaled to unit L2 norm (zero rows stay zero),
+    rotated by the k x k R of a Discretize (Alg. 5), so column c is the soft indicator of
+    cluster c."""
+    B = np.asarray(Q, np.float64)
     nr = np.sqrt((B * B).sum(axis=1))
     Qt = np.divide(B, nr[:, None], out=np.zeros_like(B), where=nr[:, None] > 0)
-    Y = Qt @ np.asarray(R, np.float64)
+    return Qt @ np.asarray(R, np.float64)
+
+
+def centre_map(labels, Xh, centres):
+    """colmap[c] = the centre assigned to cluster c: the assignment (Hungarian method) that
+    maximises the total cosine between the clusters' mean attribute vectors and the centres.
+    An empty cluster has cosine 0 with every centre."""
     C = np.asarray(centres, np.float64)
+    k = C.shape[0]
     C = C / np.linalg.norm(C, axis=1, keepdims=True)
     cos = np.zeros((k, k))
     for c in range(k):
@@ -131,6 +130,21 @@ def warm_target(Q, R, labels, Xh, centres):
         if nm > 0:
             cos[c] = C @ (mu / nm)
     _, colmap = linear_sum_assignment(-cos)
+    return colmap
+
+
+def warm_target(Q, R, labels, Xh, centres):
+    """Training target of the warm start from one run of the plain method.
+
+    Q: n x (k+1) orthonormal block of the orthogonal iteration; R: k x k rotation of its
+    last Discretize (Alg. 5); labels: that Discretize's labels; Xh: row-normalised
+    attributes; centres: the k mixture centres shared by every graph of the family.
+    The block Q[:, 1:] is row-normalised and rotated (rotated_block); column c is then moved
+    to the centre that cluster c matches (centre_map).
+    Returns (T, colmap) with T[:, colmap[c]] = Y[:, c]."""
+    k = R.shape[0]
+    Y = rotated_block(np.asarray(Q, np.float64)[:, 1:k + 1], R)
+    colmap = centre_map(labels, Xh, centres)
     T = np.zeros_like(Y)
     T[:, colmap] = Y
     return T, colmap

@@ -84,14 +84,16 @@ _SIGS = {
     "ancka_mhc": (C.c_int, [_VP, _VP, _VP, C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_double)]),
     "ancka_cluster": (C.c_int, [_VP, C.POINTER(ancka_network), C.POINTER(ancka_params), _VP, _VP,
                                 C.POINTER(ancka_report)]),
+    "ancka_cluster_op": (C.c_int, [_VP, _VP, C.POINTER(ancka_params), _VP, _VP, C.POINTER(ancka_report)]),
     "ancka_ws_create": (C.c_int, [_VP, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_VP)]),
     "ancka_ws_destroy": (None, [_VP]),
-    "ancka_ws_features": (C.c_int, [_VP, _VP, _VP, C.c_int32, C.c_int64, C.c_int64, _VP]),
-    "ancka_ws_forward": (C.c_int, [_VP, _VP, _VP, C.c_int64, _VP, C.c_int32]),
+    "ancka_ws_features": (C.c_int, [_VP, _VP, _VP, C.c_int32, C.c_int64, C.c_int64, _VP, C.c_int64]),
+    "ancka_ws_forward": (C.c_int, [_VP, _VP, _VP, C.c_int64, C.c_int64, _VP, C.c_int32]),
     "ancka_ws_backward": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int64, _VP]),
     "ancka_ws_step": (C.c_int, [_VP, _VP, C.c_double]),
     "ancka_ws_get_params": (C.c_int, [_VP, _VP, C.c_int32, _VP, C.POINTER(C.c_int64)]),
     "ancka_ws_set_params": (C.c_int, [_VP, _VP, _VP]),
+    "ancka_ws_target": (C.c_int, [_VP, _VP, C.c_int32, C.c_int64, C.c_int32, C.c_int64, _VP, _VP, _VP]),
 }
 EXPORTED = sorted(_SIGS)
 
@@ -202,6 +204,28 @@ class Lib:
                                               _ptr(labels), R.ctypes.data, C.addressof(obj), C.addressof(it)))
         return labels, R, obj.value, it.value
 
+    def ws_features(self, op, X, device=0):
+        """U = (X^ + P_N X^) / 2 as a float n x ldu tensor (ldu = d rounded up to 4)."""
+        import torch
+        ctx = self.context(device)
+        n, d = X.shape
+        ldu = (d + 3) // 4 * 4
+        U = torch.empty((n, ldu), dtype=torch.float32, device=X.device)
+        self.check(ctx, self.ancka_ws_features(ctx, op.h, _ptr(X), self.dtype_code(X), d, X.stride(0), _ptr(U), ldu))
+        return U
+
+    def ws_target(self, Qk, k: int, R, colmap, device=0):
+        """Training target from the n x k view Qk (columns 1..k of the iteration block)."""
+        import torch
+        ctx = self.context(device)
+        n = Qk.shape[0]
+        T = torch.empty((n, k), dtype=torch.float32, device=Qk.device)
+        R = np.ascontiguousarray(R, dtype=np.float64)
+        cm = np.ascontiguousarray(colmap, dtype=np.int32)
+        self.check(ctx, self.ancka_ws_target(ctx, _ptr(Qk), self.dtype_code(Qk), n, k, Qk.stride(0), R.ctypes.data,
+                                             cm.ctypes.data, _ptr(T)))
+        return T
+
     def default_params(self, **kw):
         p = self.ancka_default_params()
         for k_, v in kw.items():
@@ -212,18 +236,24 @@ class Lib:
             setattr(p, k_, v)
         return p
 
-    def cluster(self, net_struct, params, zwarm=None, trace_capacity=1024, device=0):
+    def cluster(self, net_struct, params, zwarm=None, trace_capacity=1024, device=0, op=None):
+        """Whole method on a network (or, with op, from a built operator).  Returns (labels, info)."""
         import torch
         ctx = self.context(device)
-        labels = torch.empty(net_struct.n, dtype=torch.int32, device="cuda")
+        n = op.n if op is not None else net_struct.n
+        labels = torch.empty(n, dtype=torch.int32, device="cuda")
         rep = ancka_report()
         tt = (C.c_int32 * trace_capacity)()
         tp = (C.c_double * trace_capacity)()
         rep.trace_capacity = trace_capacity
         rep.trace_t = C.cast(tt, C.POINTER(C.c_int32))
         rep.trace_phi = C.cast(tp, C.POINTER(C.c_double))
-        self.check(ctx, self.ancka_cluster(ctx, C.byref(net_struct), C.byref(params), _ptr(zwarm), _ptr(labels),
-                                           C.byref(rep)))
+        if op is not None:
+            self.check(ctx, self.ancka_cluster_op(ctx, op.h, C.byref(params), _ptr(zwarm), _ptr(labels),
+                                                  C.byref(rep)))
+        else:
+            self.check(ctx, self.ancka_cluster(ctx, C.byref(net_struct), C.byref(params), _ptr(zwarm),
+                                               _ptr(labels), C.byref(rep)))
         m = min(rep.trace_len, trace_capacity)
         info = {
             "iterations": rep.iterations, "stop_reason": STOP_REASONS[rep.stop_reason], "best_phi": rep.best_phi,
@@ -299,6 +329,72 @@ class Op:
         phi = C.c_double()
         self.lib.check(ctx, self.lib.ancka_mhc(ctx, self.h, _ptr(labels), k, alpha, gamma, C.byref(phi)))
         return phi.value
+
+
+class WarmStart:
+    """Owning handle of an ancka_ws model (MLP d -> h1 -> h2 -> k)."""
+
+    def __init__(self, lib: Lib, d: int, h1: int, h2: int, k: int, seed: int = 0, device=0):
+        self.lib, self.d, self.h1, self.h2, self.k, self.device = lib, d, h1, h2, k, device
+        ctx = lib.context(device)
+        h = _VP()
+        lib.check(ctx, lib.ancka_ws_create(ctx, d, h1, h2, k, seed, C.byref(h)))
+        self.h = h
+        cnt = C.c_int64()
+        lib.check(ctx, lib.ancka_ws_get_params(ctx, h, 2, None, C.byref(cnt)))
+        self.count = cnt.value
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.lib.ancka_ws_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def shapes(self):
+        return [(self.d, self.h1), (self.h1,), (self.h1, self.h2), (self.h2,), (self.h2, self.k), (self.k,)]
+
+    def get(self, which: int = 2):
+        """Parameters as a list [W1, b1, W2, b2, W3, b3] of float32 arrays (which: 0 forward
+        values, 1 gradients, 2 master weights)."""
+        ctx = self.lib.context(self.device)
+        flat = np.zeros(self.count, dtype=np.float32)
+        cnt = C.c_int64()
+        self.lib.check(ctx, self.lib.ancka_ws_get_params(ctx, self.h, which, flat.ctypes.data, C.byref(cnt)))
+        out, o = [], 0
+        for sh in self.shapes():
+            sz = int(np.prod(sh))
+            out.append(flat[o:o + sz].reshape(sh).copy())
+            o += sz
+        return out
+
+    def set(self, params):
+        ctx = self.lib.context(self.device)
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(p, np.float32).ravel() for p in params]))
+        if flat.size != self.count:
+            raise ValueError(f"expected {self.count} parameters, got {flat.size}")
+        self.lib.check(ctx, self.lib.ancka_ws_set_params(ctx, self.h, flat.ctypes.data))
+
+    def forward(self, U, n=None, keep_acts=False):
+        import torch
+        ctx = self.lib.context(self.device)
+        n = U.shape[0] if n is None else n
+        Z = torch.empty((n, self.k), dtype=torch.float32, device=U.device)
+        self.lib.check(ctx, self.lib.ancka_ws_forward(ctx, self.h, _ptr(U), n, U.stride(0), _ptr(Z),
+                                                      1 if keep_acts else 0))
+        return Z
+
+    def backward(self, Z, T, want_loss=True):
+        ctx = self.lib.context(self.device)
+        loss = C.c_double()
+        self.lib.check(ctx, self.lib.ancka_ws_backward(ctx, self.h, _ptr(Z), _ptr(T), Z.shape[0],
+                                                       C.addressof(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def step(self, lr: float):
+        ctx = self.lib.context(self.device)
+        self.lib.check(ctx, self.lib.ancka_ws_step(ctx, self.h, lr))
 
 
 def upload_attributes(X: np.ndarray, x_dtype: str, device="cuda"):

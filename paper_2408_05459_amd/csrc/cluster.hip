@@ -1,5 +1,5 @@
-// Greedy initial BCM (Alg. 3; Alg. 4 lines 3-11), multi-hop conductance (Alg. 2; Alg. 4 lines
-// 19-21) and the whole method (Alg. 4) on gfx950.  The host only sequences kernels and reads a
+// Greedy initial BCM (Alg. 3 and the greedy start of Alg. 4), multi-hop conductance (Alg. 2 and its
+// use in Alg. 4) and the whole method (Alg. 4) on gfx950.  The host only sequences kernels and reads a
 // few scalars every tau iterations (phi, ||Q^(t) - Q^(t-1)||_F, the Discretize flag).
 #include <chrono>
 #include <cmath>
@@ -14,7 +14,7 @@ constexpr int TOPK_T = 256;
 constexpr int TOPK_CHUNK = 4096;
 
 // key = (degree << 32) | (0xffffffff - index): the largest key is the largest degree with the
-// smallest index, the centre order of Alg. 4 line 3
+// smallest index, the centre order of Alg. 4, choice of the centres
 __device__ __forceinline__ unsigned long long centre_key(int64_t deg, int64_t i) {
   return ((unsigned long long)deg << 32) | (unsigned long long)(0xffffffffu - (uint32_t)i);
 }
@@ -305,29 +305,19 @@ ancka_status ancka_mhc(ancka_ctx* ctx, const ancka_op* op, const int32_t* labels
   return mhc_host(ctx, op, labels, k, alpha, gamma, phi);
 }
 
-ancka_status ancka_cluster(ancka_ctx* ctx, const ancka_network* net, const ancka_params* prm, const float* zwarm,
-                           int32_t* labels, ancka_report* rep) {
-  if (!ctx || !net || !prm || !labels) return ANCKA_ERR_INVALID_ARG;
-  const ancka_params& p = *prm;
-  const int64_t n = net->n;
+}  // extern "C"
+
+namespace {
+
+// Alg. 4 from the greedy start on on a built operator.  R: report with its trace buffers set; ph: phase times
+// (the KNN and operator slots are left to the caller).
+ancka_status cluster_loop(ancka_ctx* ctx, const ancka_op* op, const ancka_params& p, const float* zwarm,
+                          int32_t* labels, ancka_report* R, double* ph) {
+  const int64_t n = op->n;
   const int k = p.k;
-  if (k < 1 || k + 1 > 64 || k > n || p.K < 1 || p.K > n - 1 || p.alpha < 0.0 || p.alpha > 1.0 || p.beta < 0.0 ||
-      p.beta > 1.0 || p.gamma < 1 || p.tau < 1 || p.T_i < 0 || p.T_a < 0 || p.disc_max_iter < 1 || !net->X ||
-      (p.q_dtype != ANCKA_F32 && p.q_dtype != ANCKA_F64))
-    return set_err(ctx, ANCKA_ERR_INVALID_ARG, "ancka_cluster: invalid parameters (n=%lld k=%d K=%d)", (long long)n, k,
-                   p.K);
-  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, ANCKA_ERR_HIP, "hipSetDevice");
-  double ph[ANCKA_NPHASES] = {0};
-  ancka_report local;
-  ancka_report* R = rep ? rep : &local;
-  const int cap = rep ? rep->trace_capacity : 0;
-  int32_t* tr_t = rep ? rep->trace_t : nullptr;
-  double* tr_phi = rep ? rep->trace_phi : nullptr;
-  *R = ancka_report{};
-  R->trace_capacity = cap;
-  R->trace_t = tr_t;
-  R->trace_phi = tr_phi;
-  R->phi_init_warm = std::numeric_limits<double>::quiet_NaN();
+  const int cap = R->trace_capacity;
+  int32_t* tr_t = R->trace_t;
+  double* tr_phi = R->trace_phi;
   auto trace = [&](int t, double phi) {
     if (R->trace_len < cap && tr_t && tr_phi) {
       tr_t[R->trace_len] = t;
@@ -335,29 +325,9 @@ ancka_status ancka_cluster(ancka_ctx* ctx, const ancka_network* net, const ancka
     }
     R->trace_len++;
   };
+  double t0 = 0.0;
 
-  // ---- KNN graph (Alg. 6)
-  double t0 = now_ms();
-  const bool f64sim = p.knn_mode == ANCKA_KNN_EXACT_F64;
-  int32_t* nidx = nullptr;
-  void* nsim = nullptr;
-  ST_TRY(ws_get_t(ctx, "cl_nidx", (size_t)n * p.K, &nidx));
-  ST_TRY(ws_get(ctx, "cl_nsim", (size_t)n * p.K * (f64sim ? 8 : 4), &nsim));
-  ST_TRY(ancka_knn(ctx, net->X, net->xdtype, n, net->d, net->ldx, p.K, p.knn_mode, nidx, nsim, &R->knn));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  ph[ANCKA_PHASE_KNN] = now_ms() - t0;
-
-  // ---- operator (Alg. 4 lines 1-2)
-  t0 = now_ms();
-  ancka_op* op = nullptr;
-  ST_TRY(ancka_build_operator(ctx, net, nidx, nsim, f64sim ? ANCKA_F64 : ANCKA_F32, p.K, p.beta, p.q_dtype, &op));
-  struct OpGuard {
-    ancka_op* o;
-    ~OpGuard() { ancka_op_destroy(o); }
-  } guard{op};
-  ph[ANCKA_PHASE_OPERATOR] = now_ms() - t0;
-
-  // ---- initial BCM (Alg. 4 lines 3-11) and its MHC
+  // ---- initial BCM (Alg. 4, greedy start) and its MHC
   t0 = now_ms();
   const int64_t ldq = pad_ld(k + 1, p.q_dtype);
   const size_t es = p.q_dtype == ANCKA_F64 ? 8 : 4;
@@ -388,7 +358,7 @@ ancka_status ancka_cluster(ancka_ctx* ctx, const ancka_network* net, const ancka
   }
   R->init_used = warm ? 1 : 0;
 
-  // ---- starting block (Alg. 4 lines 12-13)
+  // ---- starting block (Alg. 4, starting block)
   t0 = now_ms();
   void *Q = nullptr, *Qn = nullptr, *Z = nullptr;
   double* dq2 = nullptr;
@@ -406,7 +376,7 @@ ancka_status ancka_cluster(ancka_ctx* ctx, const ancka_network* net, const ancka
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   ph[warm ? ANCKA_PHASE_WARM : ANCKA_PHASE_INIT] += now_ms() - t0;
 
-  // ---- main loop (Alg. 4 lines 14-24)
+  // ---- main loop (Alg. 4, main loop)
   double best_phi = phi0;
   int best_t = 0;
   std::vector<double> hist{phi0};
@@ -471,6 +441,89 @@ ancka_status ancka_cluster(ancka_ctx* ctx, const ancka_network* net, const ancka
   R->stop_reason = reason;
   R->best_phi = best_phi;
   R->best_t = best_t;
+  return ANCKA_OK;
+}
+
+bool params_ok(const ancka_params& p, int64_t n) {
+  const int k = p.k;
+  return !(k < 1 || k + 1 > 64 || k > n || p.K < 1 || p.K > n - 1 || p.alpha < 0.0 || p.alpha > 1.0 || p.beta < 0.0 ||
+           p.beta > 1.0 || p.gamma < 1 || p.tau < 1 || p.T_i < 0 || p.T_a < 0 || p.disc_max_iter < 1 ||
+           (p.q_dtype != ANCKA_F32 && p.q_dtype != ANCKA_F64));
+}
+
+void report_init(ancka_report* R) {
+  const int cap = R->trace_capacity;
+  int32_t* tr_t = R->trace_t;
+  double* tr_phi = R->trace_phi;
+  *R = ancka_report{};
+  R->trace_capacity = cap;
+  R->trace_t = tr_t;
+  R->trace_phi = tr_phi;
+  R->phi_init_warm = std::numeric_limits<double>::quiet_NaN();
+}
+
+}  // namespace
+
+extern "C" {
+
+ancka_status ancka_cluster_op(ancka_ctx* ctx, const ancka_op* op, const ancka_params* prm, const float* zwarm,
+                              int32_t* labels, ancka_report* rep) {
+  if (!ctx || !op || !prm || !labels) return ANCKA_ERR_INVALID_ARG;
+  if (!params_ok(*prm, op->n) || prm->q_dtype != op->dtype)
+    return set_err(ctx, ANCKA_ERR_INVALID_ARG, "ancka_cluster_op: invalid parameters (n=%lld k=%d, q_dtype %d, op %d)",
+                   (long long)op->n, prm->k, prm->q_dtype, op->dtype);
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, ANCKA_ERR_HIP, "hipSetDevice");
+  ancka_report local;
+  local.trace_capacity = 0;
+  local.trace_t = nullptr;
+  local.trace_phi = nullptr;
+  ancka_report* R = rep ? rep : &local;
+  report_init(R);
+  double ph[ANCKA_NPHASES] = {0};
+  ST_TRY(cluster_loop(ctx, op, *prm, zwarm, labels, R, ph));
+  for (int i = 0; i < ANCKA_NPHASES; i++) R->phase_ms[i] = ph[i];
+  return ANCKA_OK;
+}
+
+ancka_status ancka_cluster(ancka_ctx* ctx, const ancka_network* net, const ancka_params* prm, const float* zwarm,
+                           int32_t* labels, ancka_report* rep) {
+  if (!ctx || !net || !prm || !labels) return ANCKA_ERR_INVALID_ARG;
+  const ancka_params& p = *prm;
+  const int64_t n = net->n;
+  if (!params_ok(p, n) || !net->X)
+    return set_err(ctx, ANCKA_ERR_INVALID_ARG, "ancka_cluster: invalid parameters (n=%lld k=%d K=%d)", (long long)n,
+                   p.k, p.K);
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, ANCKA_ERR_HIP, "hipSetDevice");
+  double ph[ANCKA_NPHASES] = {0};
+  ancka_report local;
+  local.trace_capacity = 0;
+  local.trace_t = nullptr;
+  local.trace_phi = nullptr;
+  ancka_report* R = rep ? rep : &local;
+  report_init(R);
+
+  // ---- KNN graph (Alg. 6)
+  double t0 = now_ms();
+  const bool f64sim = p.knn_mode == ANCKA_KNN_EXACT_F64;
+  int32_t* nidx = nullptr;
+  void* nsim = nullptr;
+  ST_TRY(ws_get_t(ctx, "cl_nidx", (size_t)n * p.K, &nidx));
+  ST_TRY(ws_get(ctx, "cl_nsim", (size_t)n * p.K * (f64sim ? 8 : 4), &nsim));
+  ST_TRY(ancka_knn(ctx, net->X, net->xdtype, n, net->d, net->ldx, p.K, p.knn_mode, nidx, nsim, &R->knn));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  ph[ANCKA_PHASE_KNN] = now_ms() - t0;
+
+  // ---- operator (Alg. 4, operator construction)
+  t0 = now_ms();
+  ancka_op* op = nullptr;
+  ST_TRY(ancka_build_operator(ctx, net, nidx, nsim, f64sim ? ANCKA_F64 : ANCKA_F32, p.K, p.beta, p.q_dtype, &op));
+  struct OpGuard {
+    ancka_op* o;
+    ~OpGuard() { ancka_op_destroy(o); }
+  } guard{op};
+  ph[ANCKA_PHASE_OPERATOR] = now_ms() - t0;
+
+  ST_TRY(cluster_loop(ctx, op, p, zwarm, labels, R, ph));
   for (int i = 0; i < ANCKA_NPHASES; i++) R->phase_ms[i] = ph[i];
   return ANCKA_OK;
 }

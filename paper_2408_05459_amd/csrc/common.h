@@ -140,7 +140,7 @@ ancka_status qr_block(ancka_ctx* ctx, int dtype, const void* Z, void* Qout, int6
                       const void* Qprev, double* dq2_dev, double* R_out);
 // counts[c] = number of rows with label c (device); *bad |= 1 on a label outside [0, k)
 ancka_status count_labels(ancka_ctx* ctx, const int32_t* labels, int64_t n, int k, int32_t* counts, int* bad);
-// starting block of Alg. 4 lines 12-13 (see ancka_initial_block)
+// starting block of Alg. 4, starting block (see ancka_initial_block)
 ancka_status initial_block(ancka_ctx* ctx, const ancka_op* op, const int32_t* labels, const float* zwarm, int k,
                            void* Q, int64_t ldq);
 // Discretize of Alg. 5 (see ancka_discretize); synchronises

@@ -1,4 +1,4 @@
-// K nearest neighbours by cosine similarity (Sec. 3.1; Alg. 6 lines 1-5) on gfx950.
+// K nearest neighbours by cosine similarity (Sec. 3.1; Alg. 6, neighbour search) on gfx950.
 //
 // Modes
 //  EXACT_F64     FP64 tiles; the top-K list is final (similarity = dot / sqrt(|x_i|^2 |x_j|^2)).

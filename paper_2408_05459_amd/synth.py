@@ -306,6 +306,11 @@ def make_config(cfg: int, scale: float = 1.0, seed: Optional[int] = None):
 WARM_CENTRE_SEED = 5999
 
 
+def warm_centres(k: int = 30, d: int = 512) -> np.ndarray:
+    """Mixture centres shared by every graph of the warm-start family."""
+    return gmm_centres(k, d, 2.0, np.random.default_rng(WARM_CENTRE_SEED))
+
+
 def make_warm_graph(n: int, seed: int, k: int = 30, d: int = 512, mean_deg: float = 25.0):
     """Hypergraph family of the learned warm start (shared GMM centres)."""
     rng = np.random.default_rng(seed)
@@ -314,7 +319,7 @@ def make_warm_graph(n: int, seed: int, k: int = 30, d: int = 512, mean_deg: floa
     m = max(k, int(round(n * mean_deg / mean_size)))
     sizes = truncated_zipf_sizes(m, 2, min(50, max(2, n // k)), 2.0, rng)
     he_ptr, he_idx = hypergraph_incidence(labels, k, sizes, 0.7, rng)
-    cen = gmm_centres(k, d, 2.0, np.random.default_rng(WARM_CENTRE_SEED))
+    cen = warm_centres(k, d)
     X = gmm_attributes(labels, cen, rng, "bf16")
     net = Network(HYPERGRAPH, n, k, X, "bf16", [he_ptr], [he_idx], m=m, labels=labels,
                   name=f"hypergraph n={n} k={k} m={m} gmm d={d} (bf16)")

@@ -91,6 +91,68 @@ def cpu_baseline(net, prm, gpu_iters, gpu_checks, knn_rows=96, small_scale=0.02)
     }
 
 
+def warm_vs_cold(lib, graphs: int, n_train: int, epochs: int, lr: float, n_test: int, workers: int):
+    """Learned warm start on the n = 1M hypergraph of the warm-start family (d = 512, k = 30):
+    train the MLP on `graphs` seeded graphs of n_train nodes (targets from the plain method's
+    eigenblocks), then run the method cold and warm-started on the test graph and compare
+    iterations and wall time to reach the cold run's conductance (within 1e-4 relative)."""
+    import torch
+    from paper_2408_05459_amd import synth, warmstart
+    t0 = time.perf_counter()
+    seeds = list(range(5001, 5001 + graphs))
+    exs = warmstart.make_examples(lib, n_train, seeds, workers=workers, log=log)
+    t_data = time.perf_counter() - t0
+    ws, tl = warmstart.train(lib, exs, 512, 30, epochs=epochs, lr=lr, seed=0)
+    log(f"trained on {graphs} graphs x {n_train} rows, {epochs} epochs: loss {tl.epoch_loss[0]:.4f} -> "
+        f"{tl.epoch_loss[-1]:.4f} in {tl.seconds:.1f}s")
+    plain_iters = float(np.mean([e.iters for e in exs]))
+    del exs
+    torch.cuda.empty_cache()
+    t1 = time.perf_counter()
+    net, prm = synth.make_warm_graph(n_test, 5000)
+    log(f"generated {net.name} in {time.perf_counter() - t1:.1f}s")
+    s, keep = lib.network(net)
+    X = keep[-1]
+    warmstart.run(lib, s, X, net.k, prm)                       # first call: kernels and workspaces warm
+    lc, ic, tc = warmstart.run(lib, s, X, net.k, prm)
+    lw, iw, tw = warmstart.run(lib, s, X, net.k, prm, ws=ws)
+    target = ic["best_phi"] * (1 + 1e-4)
+    t_cold = warmstart.time_to_reach(ic, target)
+    t_warm = warmstart.time_to_reach(iw, target)
+    # end-to-end time to the cold run's objective: the same runs stopped at that iteration
+    to_target = {}
+    for tag, t_hit, model in (("cold", t_cold, None), ("warm", t_warm, ws)):
+        if t_hit is None:
+            to_target[tag] = None
+            continue
+        _, it_, tm_ = warmstart.run(lib, s, X, net.k, prm, ws=model, T_a=t_hit)
+        to_target[tag] = {"iterations": t_hit, "best_phi": it_["best_phi"], "ms": round(tm_["total"], 1)}
+    from sklearn.metrics import adjusted_rand_score
+    res = {
+        "workload": net.name, "train_graphs": graphs, "train_n": n_train, "epochs": epochs,
+        "train_loss_first_last": [round(tl.epoch_loss[0], 5), round(tl.epoch_loss[-1], 5)],
+        "train_s": round(tl.seconds, 2), "train_data_s": round(t_data, 1),
+        "train_plain_iters_mean": plain_iters,
+        "target_phi": target,
+        "to_target": to_target,
+        "speedup_to_target": (round(to_target["cold"]["ms"] / to_target["warm"]["ms"], 3)
+                              if to_target.get("cold") and to_target.get("warm") else None),
+        "cold": {"iterations": ic["iterations"], "stop": ic["stop_reason"], "best_phi": ic["best_phi"],
+                 "best_t": ic["best_t"], "iters_to_target": t_cold, "ms": {k_: round(v, 1) for k_, v in tc.items()},
+                 "ari_vs_planted": round(float(adjusted_rand_score(net.labels, lc.cpu().numpy())), 4)},
+        "warm": {"iterations": iw["iterations"], "stop": iw["stop_reason"], "best_phi": iw["best_phi"],
+                 "best_t": iw["best_t"], "iters_to_target": t_warm, "init_used": iw["init_used"],
+                 "phi_init_cold": iw["phi_init_cold"], "phi_init_warm": iw["phi_init_warm"],
+                 "ms": {k_: round(v, 1) for k_, v in tw.items()},
+                 "ari_vs_planted": round(float(adjusted_rand_score(net.labels, lw.cpu().numpy())), 4)},
+    }
+    log(f"cold: {ic['iterations']} iterations, phi {ic['best_phi']:.6f}, {tc['total']:.0f} ms; "
+        f"warm: {iw['iterations']} iterations, phi {iw['best_phi']:.6f}, {tw['total']:.0f} ms")
+    del keep, X, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +162,13 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--spmm-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start comparison")
+    ap.add_argument("--ws-graphs", type=int, default=200)
+    ap.add_argument("--ws-n", type=int, default=50000)
+    ap.add_argument("--ws-epochs", type=int, default=8)
+    ap.add_argument("--ws-lr", type=float, default=1e-3)
+    ap.add_argument("--ws-test-n", type=int, default=1000000)
+    ap.add_argument("--ws-workers", type=int, default=16)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the method's multi-GPU sharding is "
@@ -210,6 +279,8 @@ def main():
         "best_phi": last["best_phi"],
         "ari_vs_planted": round(ari_planted, 4),
     }
+    if not a.no_warm:
+        out["warm_start"] = warm_vs_cold(lib, a.ws_graphs, a.ws_n, a.ws_epochs, a.ws_lr, a.ws_test_n, a.ws_workers)
     if not a.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")
         checks = sum(1 for t, _ in last["trace"] if t > 0)

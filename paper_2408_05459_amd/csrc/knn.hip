@@ -207,15 +207,29 @@ __global__ __launch_bounds__(256) void knn_vector_kernel(const TX* __restrict__ 
 constexpr int BT_C = 64;   // candidates per tile
 constexpr int NPIV = 64;   // coarse cells of the scan order
 
-__device__ __noinline__ void insert_sorted(float* ls, int* li, int KP, float s, int jj) {
-  int p = KP - 1;
-  while (p > 0 && better<float>(s, jj, ls[p - 1], li[p - 1])) {
-    ls[p] = ls[p - 1];
-    li[p] = li[p - 1];
-    p--;
-  }
+// One query's candidate list in LDS, unsorted: kpp slots (the list length rounded up to 4;
+// padding slots hold (+inf, -1) and are never the worst), plus the record (wv, wi, wp) of its
+// worst entry under the order (score desc, index asc).  (s, jj) replaces the worst entry, then
+// the new worst is found by one pass of independent 16-byte reads.  The list ends as the top
+// entries of that total order whatever order candidates arrive in.
+__device__ __noinline__ void list_replace_worst(float* ls, int* li, int kpp, float* wv, int* wi, int* wp, float s,
+                                                int jj) {
+  const int p = *wp;
   ls[p] = s;
   li[p] = jj;
+  float bs = INFINITY;
+  int bj = INT_MIN, bp = 0;
+  for (int r = 0; r < kpp; r += 4) {
+    const float4 s4 = *(const float4*)(ls + r);
+    const int4 j4 = *(const int4*)(li + r);
+    if (s4.x < bs || (s4.x == bs && j4.x > bj)) { bs = s4.x; bj = j4.x; bp = r; }
+    if (s4.y < bs || (s4.y == bs && j4.y > bj)) { bs = s4.y; bj = j4.y; bp = r + 1; }
+    if (s4.z < bs || (s4.z == bs && j4.z > bj)) { bs = s4.z; bj = j4.z; bp = r + 2; }
+    if (s4.w < bs || (s4.w == bs && j4.w > bj)) { bs = s4.w; bj = j4.w; bp = r + 3; }
+  }
+  *wv = bs;
+  *wi = bj;
+  *wp = bp;
 }
 
 template <int DP, int QW, int NBUF>
@@ -230,14 +244,19 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
   constexpr int CHUNKS = BT_C * DP / 8; // 16-byte chunks per tile
   constexpr int CPT = CHUNKS / 256;     // chunks per thread
   static_assert(CHUNKS % 256 == 0, "tile chunks");
+  static_assert(QB % BT_C == 0, "padding to whole workgroups covers whole tiles");
 
   extern __shared__ __align__(16) unsigned char smem[];
   uint16_t* tileb = (uint16_t*)smem;                         // [NBUF][BT_C][LDR]
   float* tinv = (float*)(tileb + NBUF * BT_C * LDR);         // [NBUF][BT_C]
   int* tperm = (int*)(tinv + NBUF * BT_C);                   // [NBUF][BT_C]
   float* tmn = (float*)(tperm + NBUF * BT_C);                // [NBUF] (padded to 4)
-  float* lsim = tmn + 4;                                     // [QB][KP]
-  int* lidx = (int*)(lsim + QB * KP);                        // [QB][KP]
+  const int KPP = (KP + 3) & ~3;                             // list slots per query
+  float* lsim = tmn + 4;                                     // [QB][KPP]
+  int* lidx = (int*)(lsim + QB * KPP);                       // [QB][KPP]
+  float* lwv = (float*)(lidx + QB * KPP);                    // [QB] worst score of each list
+  int* lwi = (int*)(lwv + QB);                               // [QB] its index
+  int* lwp = lwi + QB;                                       // [QB] its slot
 
   const int tid = threadIdx.x;
   const int wave = tid / ANCKA_WAVE;
@@ -246,9 +265,15 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
   const int half = lane / 32;
   const int64_t q0 = (int64_t)blockIdx.x * QB;
 
-  for (int e = tid; e < QB * KP; e += 256) {
-    lsim[e] = -INFINITY;
-    lidx[e] = INT_MAX;
+  for (int e = tid; e < QB * KPP; e += 256) {
+    const bool pad = (e % KPP) >= KP;
+    lsim[e] = pad ? INFINITY : -INFINITY;
+    lidx[e] = pad ? -1 : INT_MAX;
+  }
+  for (int q = tid; q < QB; q += 256) {
+    lwv[q] = -INFINITY;
+    lwi[q] = INT_MAX;
+    lwp[q] = 0;
   }
 
   // query fragments: lane holds 8 bf16 of query row (l32) at k = ks*16 + half*8
@@ -256,70 +281,70 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
   float thr[NQB];
   int qloc[NQB];
   int qorig[NQB];
+  // Xs, invs and perm are padded with zero rows (invs 0, perm -1) to whole workgroups, so no
+  // load below needs a bounds check; padding rows never become candidates (invs 0) and their
+  // queries never accept one (threshold +inf).
 #pragma unroll
   for (int qb = 0; qb < NQB; qb++) {
     qloc[qb] = wave * QW + qb * 32 + l32;
     const int64_t qs = q0 + qloc[qb];
-    const bool inb = qs < n;
-    qorig[qb] = inb ? perm[qs] : -1;
-    thr[qb] = (inb && invs[inb ? qs : 0] > 0.0f) ? -INFINITY : INFINITY;
+    qorig[qb] = perm[qs];
+    thr[qb] = invs[qs] > 0.0f ? -INFINITY : INFINITY;
 #pragma unroll
     for (int ks = 0; ks < KS; ks++) {
-      if (inb) {
-        const uint4 v = *(const uint4*)(Xs + qs * DP + ks * 16 + half * 8);
-        bq[qb][ks] = __builtin_bit_cast(bf16x8, v);
-      } else {
-        bq[qb][ks] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
-      }
+      const uint4 v = *(const uint4*)(Xs + qs * DP + ks * 16 + half * 8);
+      bq[qb][ks] = __builtin_bit_cast(bf16x8, v);
     }
   }
 
   const int64_t ntiles = cdiv(n, BT_C);
   const int64_t t0 = wg_start[blockIdx.x];
+  // this thread's 16-byte chunks of a tile: element offsets in global memory and in LDS
+  int goff[CPT], loff[CPT];
+#pragma unroll
+  for (int u = 0; u < CPT; u++) {
+    const int c = u * 256 + tid;
+    const int r = c / (DP / 8), c8 = c % (DP / 8);
+    goff[u] = r * DP + c8 * 8;
+    loff[u] = r * LDR + c8 * 8;
+  }
   uint4 pre[CPT];
   float pre_inv = 0.0f;
   int pre_perm = -1;
   float pre_tmn = INFINITY;
-  auto prefetch = [&](int64_t tt) {
-    if (tid == 0) pre_tmn = tile_min[tt];
-#pragma unroll
-    for (int u = 0; u < CPT; u++) {
-      const int c = u * 256 + tid;
-      const int r = c / (DP / 8), c8 = c % (DP / 8);
-      const int64_t j = tt * BT_C + r;
-      pre[u] = (j < n) ? *(const uint4*)(Xs + j * DP + c8 * 8) : make_uint4(0, 0, 0, 0);
-    }
-    if (tid < BT_C) {
-      const int64_t j = tt * BT_C + tid;
-      pre_inv = (j < n) ? invs[j] : 0.0f;
-      pre_perm = (j < n) ? perm[j] : -1;
-    }
-  };
-  auto commit = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < CPT; u++) {
-      const int c = u * 256 + tid;
-      const int r = c / (DP / 8), c8 = c % (DP / 8);
-      *(uint4*)(tileb + (buf * BT_C + r) * LDR + c8 * 8) = pre[u];
-    }
-    if (tid < BT_C) {
-      tinv[buf * BT_C + tid] = pre_inv;
-      tperm[buf * BT_C + tid] = pre_perm;
-    }
-    if (tid == 0) tmn[buf] = pre_tmn;
-  };
-  auto tile_at = [&](int64_t t) {
-    int64_t tt = t0 + t;
-    return tt >= ntiles ? tt - ntiles : tt;
-  };
+  // tile t of this workgroup's scan: (t0 + t) mod ntiles.  (The always-true tt < ntiles select
+  // in KNN_PREFETCH keeps `pre` in registers: without it the compiler places it in scratch.)
+#define KNN_TILE_AT(t) ((t0 + (t)) >= ntiles ? (t0 + (t)) - ntiles : (t0 + (t)))
+#define KNN_PREFETCH(tt)                                                                      \
+  {                                                                                           \
+    const int64_t tt_ = (tt);                                                                 \
+    if (tid == 0) pre_tmn = tile_min[tt_];                                                    \
+    const uint16_t* src_ = Xs + tt_ * (int64_t)(BT_C * DP);                                   \
+    _Pragma("unroll") for (int u = 0; u < CPT; u++) pre[u] = (tt_ < ntiles) ? *(const uint4*)(src_ + goff[u]) : make_uint4(0, 0, 0, 0); \
+    if (tid < BT_C) {                                                                         \
+      pre_inv = invs[tt_ * BT_C + tid];                                                       \
+      pre_perm = perm[tt_ * BT_C + tid];                                                      \
+    }                                                                                         \
+  }
+#define KNN_COMMIT(b)                                                                         \
+  {                                                                                           \
+    const int b_ = (b);                                                                       \
+    uint16_t* dst_ = tileb + b_ * BT_C * LDR;                                                 \
+    _Pragma("unroll") for (int u = 0; u < CPT; u++) *(uint4*)(dst_ + loff[u]) = pre[u];       \
+    if (tid < BT_C) {                                                                         \
+      tinv[b_ * BT_C + tid] = pre_inv;                                                        \
+      tperm[b_ * BT_C + tid] = pre_perm;                                                      \
+    }                                                                                         \
+    if (tid == 0) tmn[b_] = pre_tmn;                                                          \
+  }
 
-  prefetch(tile_at(0));
-  commit(0);
+  KNN_PREFETCH(KNN_TILE_AT(0));
+  KNN_COMMIT(0);
   __syncthreads();
 
   for (int64_t t = 0; t < ntiles; t++) {
     const int buf = NBUF == 2 ? (int)(t & 1) : 0;
-    if (t + 1 < ntiles) prefetch(tile_at(t + 1));
+    if (t + 1 < ntiles) KNN_PREFETCH(KNN_TILE_AT(t + 1));
 
     f32x16 acc[2][NQB];
 #pragma unroll
@@ -360,12 +385,12 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
       if (__ballot(hit)) {
         const int q = qloc[qb];
         const int qi = qorig[qb];
-        float* ls = lsim + q * KP;
-        int* li = lidx + q * KP;
+        float* ls = lsim + q * KPP;
+        int* li = lidx + q * KPP;
         for (int h = 0; h < 2; h++) {
           if (hit && half == h) {
-            float tcur = ls[KP - 1];
-            int tcur_i = li[KP - 1];
+            float tcur = lwv[q];
+            int tcur_i = lwi[q];
 #pragma unroll
             for (int cb = 0; cb < 2; cb++) {
 #pragma unroll
@@ -379,9 +404,9 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
                 for (int e = 0; e < 4; e++) {
                   const float s = acc[cb][qb][4 * g + e] * ivs[e];
                   if (ivs[e] > 0.0f && jps[e] != qi && better<float>(s, jps[e], tcur, tcur_i)) {
-                    insert_sorted(ls, li, KP, s, jps[e]);
-                    tcur = ls[KP - 1];
-                    tcur_i = li[KP - 1];
+                    list_replace_worst(ls, li, KPP, lwv + q, lwi + q, lwp + q, s, jps[e]);
+                    tcur = lwv[q];
+                    tcur_i = lwi[q];
                   }
                 }
               }
@@ -389,33 +414,51 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
           }
           __threadfence_block();
         }
-        if (thr[qb] != INFINITY) thr[qb] = ls[KP - 1];
+        if (thr[qb] != INFINITY) thr[qb] = lwv[q];
       }
     }
 
     if (NBUF == 2) {
-      if (t + 1 < ntiles) commit(buf ^ 1);
+      if (t + 1 < ntiles) KNN_COMMIT(buf ^ 1);
       __syncthreads();
     } else {
       __syncthreads();            // every wave is done with the single buffer
-      if (t + 1 < ntiles) commit(0);
+      if (t + 1 < ntiles) KNN_COMMIT(0);
       __syncthreads();
     }
   }
 
-  // write the lists (one thread per query), scores scaled by 1/|x_i| to cosines
+  // sort each list (one thread per query), then write it with scores scaled by 1/|x_i| to cosines
   for (int q = tid; q < QB; q += 256) {
     const int64_t qs = q0 + q;
     if (qs >= n) continue;
+    float* ls = lsim + q * KPP;
+    int* li = lidx + q * KPP;
+    for (int a = 1; a < KP; a++) {
+      const float sa = ls[a];
+      const int ja = li[a];
+      int b = a;
+      while (b > 0 && better<float>(sa, ja, ls[b - 1], li[b - 1])) {
+        ls[b] = ls[b - 1];
+        li[b] = li[b - 1];
+        b--;
+      }
+      ls[b] = sa;
+      li[b] = ja;
+    }
     const int qi = perm[qs];
     const float iq = invs[qs];
     for (int r = 0; r < KP; r++) {
-      const int j = lidx[q * KP + r];
+      const int j = li[r];
       cand_idx[(int64_t)qi * KP + r] = (j == INT_MAX) ? -1 : j;
-      cand_sim[(int64_t)qi * KP + r] = (j == INT_MAX) ? 0.0f : lsim[q * KP + r] * iq;
+      cand_sim[(int64_t)qi * KP + r] = (j == INT_MAX) ? 0.0f : ls[r] * iq;
     }
   }
 }
+
+#undef KNN_TILE_AT
+#undef KNN_PREFETCH
+#undef KNN_COMMIT
 
 // cell of each row: the most similar of NPIV pivot rows (dot with the pivot scaled by its inverse
 // norm; ties to the smaller pivot).  Pivots are held in LDS as bf16; a thread owns a row and
@@ -476,18 +519,28 @@ __global__ __launch_bounds__(256) void cell_assign_kernel(const TX* __restrict__
   vals[i] = (uint64_t)i;
 }
 
-// Xs[p] = zero-padded bf16 row X[perm[p]], invs[p] = 1/|x_perm[p]|, perm[p]
-__global__ __launch_bounds__(256) void gather_sorted_kernel(const uint16_t* __restrict__ X, int64_t n, int64_t d,
+// Xs[p] = zero-padded bf16 row X[perm[p]], invs[p] = 1/|x_perm[p]|, perm[p]; rows n..npad-1
+// are zero with invs 0 and perm -1
+__global__ __launch_bounds__(256) void gather_sorted_kernel(const uint16_t* __restrict__ X, int64_t n, int64_t npad,
+                                                            int64_t d,
                                                             int64_t ldx, const uint64_t* __restrict__ order,
                                                             const float* __restrict__ invn, int DP,
                                                             uint16_t* __restrict__ Xs, float* __restrict__ invs,
                                                             int32_t* __restrict__ perm) {
   const int64_t p = (int64_t)blockIdx.x * 4 + threadIdx.x / ANCKA_WAVE;
   const int lane = threadIdx.x % ANCKA_WAVE;
-  if (p >= n) return;
+  if (p >= npad) return;
+  uint16_t* xs = Xs + p * (int64_t)DP;
+  if (p >= n) {   // padding row
+    for (int c = lane; c < DP; c += ANCKA_WAVE) xs[c] = (uint16_t)0;
+    if (lane == 0) {
+      invs[p] = 0.0f;
+      perm[p] = -1;
+    }
+    return;
+  }
   const int64_t i = (int64_t)order[p];
   const uint16_t* xr = X + i * ldx;
-  uint16_t* xs = Xs + p * (int64_t)DP;
   for (int c = lane; c < DP; c += ANCKA_WAVE) xs[c] = (c < d) ? xr[c] : (uint16_t)0;
   if (lane == 0) {
     invs[p] = invn[i];
@@ -701,7 +754,8 @@ template <int DP, int QW, int NBUF>
 ancka_status run_bf16_t(ancka_ctx* ctx, const uint16_t* Xs, int64_t n, const float* invs, const int32_t* perm,
                         const float* tmin, const int32_t* wg_start, int KP, int32_t* cidx, float* csim) {
   constexpr int QB = 4 * QW;
-  const size_t sm = (size_t)NBUF * BT_C * (DP + 8) * 2 + 2 * NBUF * BT_C * 4 + 16 + (size_t)QB * KP * 8;
+  const int KPP = (KP + 3) & ~3;
+  const size_t sm = (size_t)NBUF * BT_C * (DP + 8) * 2 + 2 * NBUF * BT_C * 4 + 16 + (size_t)QB * KPP * 8 + (size_t)QB * 12;
   static bool attr_set = false;
   if (!attr_set) {
     HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_bf16_kernel<DP, QW, NBUF>,
@@ -810,10 +864,12 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
       ST_TRY(ws_get_t(ctx, "knn_keys", (size_t)n, &keys));
       ST_TRY(ws_get_t(ctx, "knn_order", (size_t)n, &order));
       ST_TRY(ws_get_t(ctx, "knn_piv", NPIV, &piv));
-      ST_TRY(ws_get_t(ctx, "knn_invs", (size_t)n, &invs));
-      ST_TRY(ws_get_t(ctx, "knn_perm", (size_t)n, &perm));
+      // sorted copies padded to whole workgroups (QB is a multiple of the tile height)
+      const int64_t npad = nwg * QB;
+      ST_TRY(ws_get_t(ctx, "knn_invs", (size_t)npad, &invs));
+      ST_TRY(ws_get_t(ctx, "knn_perm", (size_t)npad, &perm));
       ST_TRY(ws_get_t(ctx, "knn_wgs", (size_t)nwg, &wgs));
-      ST_TRY(ws_get_t(ctx, "knn_xs", (size_t)n * DP, &Xs));
+      ST_TRY(ws_get_t(ctx, "knn_xs", (size_t)npad * DP, &Xs));
       // pivots: evenly spaced rows (a zero pivot row only yields an unused cell)
       int64_t hp[NPIV];
       for (int p = 0; p < NPIV; p++) hp[p] = (int64_t)((double)p * (double)n / NPIV);
@@ -829,8 +885,8 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
           (const uint16_t*)(const void*)X, n, d, ldx, invn, piv, keys, nrm, order);
       LAUNCH_CHECK(ctx);
       ST_TRY(radix_sort_u64(ctx, keys, order, n, 40));
-      gather_sorted_kernel<<<(unsigned)cdiv(n, 4), 256, 0, ctx->stream>>>((const uint16_t*)(const void*)X, n, d, ldx,
-                                                                          order, invn, DP, Xs, invs, perm);
+      gather_sorted_kernel<<<(unsigned)cdiv(npad, 4), 256, 0, ctx->stream>>>((const uint16_t*)(const void*)X, n, npad,
+                                                                             d, ldx, order, invn, DP, Xs, invs, perm);
       LAUNCH_CHECK(ctx);
       tile_min_sorted_kernel<<<(unsigned)cdiv(nt, 256), 256, 0, ctx->stream>>>(invs, n, BT_C, tmin, nt);
       LAUNCH_CHECK(ctx);

@@ -78,21 +78,19 @@ def generate(n: int, seeds: List[int], workers: int = 0):
             yield s, net, prm
 
 
-def plain_block(lib: binding.Lib, s, X, k: int, prm: synth.RunParams, max_t: int = 300):
-    """Run the plain method's steps: KNN graph, operator, greedy start, orthogonal iteration
-    until Eq. (tcond-1) holds at a check every tau iterations, Discretize.  Returns
-    (op, Q, labels, R, t)."""
+def plain_block(lib: binding.Lib, s, X, k: int, prm: synth.RunParams):
+    """The plain method's final eigenblock: the method runs to its own termination (Eqs.
+    tcond-1/tcond-2) from the greedy start, then the block of that iteration is rebuilt from the
+    same start (both steps are deterministic) and discretized.  Returns (op, Q, labels, R, t)."""
     idx, sim, _ = lib.knn(X, prm.K, prm.knn_mode)
     op = lib.build_operator(s, idx, sim, prm.K, prm.beta, prm.q_dtype)
     del idx, sim
+    _, info = lib.cluster(None, params_for(lib, k, prm), op=op)
+    t = info["iterations"]
     y0 = op.init_bcm(k, prm.alpha, prm.T_i)
     Q = op.initial_block(k, labels=y0)
-    t = 0
-    while t < max_t:
-        _, dq = op.orth_iter(Q, k + 1, prm.tau)
-        t += prm.tau
-        if dq < prm.eps_q:
-            break
+    if t > 0:
+        op.orth_iter(Q, k + 1, t)
     labels, R, _, _ = lib.discretize(Q[:, 1:], k, max_iter=prm.disc_max_iter)
     return op, Q, labels, R, t
 
@@ -158,13 +156,13 @@ def mean_loss(ws: binding.WarmStart, examples: List[Example]) -> float:
     return tot / len(examples)
 
 
-def run(lib: binding.Lib, s, X, k: int, prm: synth.RunParams, ws: Optional[binding.WarmStart] = None):
+def run(lib: binding.Lib, s, X, k: int, prm: synth.RunParams, ws: Optional[binding.WarmStart] = None, **over):
     """One run of the method on an uploaded network, cold (ws None) or warm-started.
 
     Both runs build the KNN graph and the operator once; the warm run then aggregates the
     features with the operator's walk, evaluates the MLP and hands its block to the loop
-    (which keeps the greedy start if that has the lower conductance).  Returns
-    (labels, info, timings_ms)."""
+    (which keeps the greedy start if that has the lower conductance).  `over` overrides run
+    parameters (e.g. T_a).  Returns (labels, info, timings_ms)."""
     import torch
     tm = {}
     torch.cuda.synchronize()
@@ -184,7 +182,7 @@ def run(lib: binding.Lib, s, X, k: int, prm: synth.RunParams, ws: Optional[bindi
         tm["features_mlp"] = (time.perf_counter() - t2) * 1e3
         del U
     t3 = time.perf_counter()
-    labels, info = lib.cluster(None, params_for(lib, k, prm), zwarm=zwarm, op=op)
+    labels, info = lib.cluster(None, params_for(lib, k, prm, **over), zwarm=zwarm, op=op)
     tm["loop"] = (time.perf_counter() - t3) * 1e3
     tm["total"] = (time.perf_counter() - t0) * 1e3
     return labels, info, tm

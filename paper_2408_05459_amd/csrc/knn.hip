@@ -212,7 +212,7 @@ constexpr int NPIV = 64;   // coarse cells of the scan order
 // worst entry under the order (score desc, index asc).  (s, jj) replaces the worst entry, then
 // the new worst is found by one pass of independent 16-byte reads.  The list ends as the top
 // entries of that total order whatever order candidates arrive in.
-__device__ __noinline__ void list_replace_worst(float* ls, int* li, int kpp, float* wv, int* wi, int* wp, float s,
+__device__ __forceinline__ void list_replace_worst(float* ls, int* li, int kpp, float* wv, int* wi, int* wp, float s,
                                                 int jj) {
   const int p = *wp;
   ls[p] = s;
@@ -391,20 +391,21 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
           if (hit && half == h) {
             float tcur = lwv[q];
             int tcur_i = lwi[q];
+            // a candidate can enter only if its raw score reaches the tile bound fth (fth is at
+            // most the list's worst score times the smallest candidate norm of the tile), so the
+            // norm and index of a candidate are read only when that test passes
 #pragma unroll
             for (int cb = 0; cb < 2; cb++) {
 #pragma unroll
-              for (int g = 0; g < 4; g++) {
-                const int cl0 = cb * 32 + 8 * g + 4 * half;
-                const float4 iv4 = *(const float4*)(tinv + buf * BT_C + cl0);
-                const int4 jp4 = *(const int4*)(tperm + buf * BT_C + cl0);
-                const float ivs[4] = {iv4.x, iv4.y, iv4.z, iv4.w};
-                const int jps[4] = {jp4.x, jp4.y, jp4.z, jp4.w};
-#pragma unroll
-                for (int e = 0; e < 4; e++) {
-                  const float s = acc[cb][qb][4 * g + e] * ivs[e];
-                  if (ivs[e] > 0.0f && jps[e] != qi && better<float>(s, jps[e], tcur, tcur_i)) {
-                    list_replace_worst(ls, li, KPP, lwv + q, lwi + q, lwp + q, s, jps[e]);
+              for (int i = 0; i < 16; i++) {
+                const float a = acc[cb][qb][i];
+                if (a >= fth) {
+                  const int cl = buf * BT_C + cb * 32 + 8 * (i / 4) + 4 * half + (i % 4);
+                  const float iv = tinv[cl];
+                  const int jp = tperm[cl];
+                  const float sc = a * iv;
+                  if (iv > 0.0f && jp != qi && better<float>(sc, jp, tcur, tcur_i)) {
+                    list_replace_worst(ls, li, KPP, lwv + q, lwi + q, lwp + q, sc, jp);
                     tcur = lwv[q];
                     tcur_i = lwi[q];
                   }
@@ -412,7 +413,10 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
               }
             }
           }
-          __threadfence_block();
+          // the two halves of the wave update the same lists in turn.  LDS operations of one
+          // wave execute in program order, so only the compiler must keep them in order; a
+          // memory fence here would also wait for the next tile's global loads in flight.
+          asm volatile("" ::: "memory");
         }
         if (thr[qb] != INFINITY) thr[qb] = lwv[q];
       }

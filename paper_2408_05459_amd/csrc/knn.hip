@@ -208,28 +208,38 @@ constexpr int BT_C = 64;   // candidates per tile
 constexpr int NPIV = 64;   // coarse cells of the scan order
 
 // One query's candidate list in LDS, unsorted: kpp slots (the list length rounded up to 4;
-// padding slots hold (+inf, -1) and are never the worst), plus the record (wv, wi, wp) of its
-// worst entry under the order (score desc, index asc).  (s, jj) replaces the worst entry, then
-// the new worst is found by one pass of independent 16-byte reads.  The list ends as the top
-// entries of that total order whatever order candidates arrive in.
-__device__ __forceinline__ void list_replace_worst(float* ls, int* li, int kpp, float* wv, int* wi, int* wp, float s,
-                                                int jj) {
-  const int p = *wp;
-  ls[p] = s;
-  li[p] = jj;
+// padding slots hold (+inf, -1) and are never the worst).  The caller keeps the list's worst
+// entry (score ws, index wj, slot wp) under the order (score desc, index asc) in registers.
+// (s, jj) replaces the worst entry, then the new worst is found with 16-byte reads, eight
+// entries per step.  The list ends as the top entries of that total order whatever order
+// candidates arrive in.
+__device__ __forceinline__ void list_replace_worst(float* ls, int* li, int kpp, float s, int jj, float& ws, int& wj,
+                                                   int& wp) {
+  ls[wp] = s;
+  li[wp] = jj;
   float bs = INFINITY;
   int bj = INT_MIN, bp = 0;
-  for (int r = 0; r < kpp; r += 4) {
-    const float4 s4 = *(const float4*)(ls + r);
-    const int4 j4 = *(const int4*)(li + r);
-    if (s4.x < bs || (s4.x == bs && j4.x > bj)) { bs = s4.x; bj = j4.x; bp = r; }
-    if (s4.y < bs || (s4.y == bs && j4.y > bj)) { bs = s4.y; bj = j4.y; bp = r + 1; }
-    if (s4.z < bs || (s4.z == bs && j4.z > bj)) { bs = s4.z; bj = j4.z; bp = r + 2; }
-    if (s4.w < bs || (s4.w == bs && j4.w > bj)) { bs = s4.w; bj = j4.w; bp = r + 3; }
+  for (int r = 0; r < kpp; r += 8) {
+    const float4 sa = *(const float4*)(ls + r);
+    const int4 ja = *(const int4*)(li + r);
+    float4 sb = make_float4(INFINITY, INFINITY, INFINITY, INFINITY);
+    int4 jb = make_int4(-1, -1, -1, -1);
+    if (r + 4 < kpp) {
+      sb = *(const float4*)(ls + r + 4);
+      jb = *(const int4*)(li + r + 4);
+    }
+    if (sa.x < bs || (sa.x == bs && ja.x > bj)) { bs = sa.x; bj = ja.x; bp = r; }
+    if (sa.y < bs || (sa.y == bs && ja.y > bj)) { bs = sa.y; bj = ja.y; bp = r + 1; }
+    if (sa.z < bs || (sa.z == bs && ja.z > bj)) { bs = sa.z; bj = ja.z; bp = r + 2; }
+    if (sa.w < bs || (sa.w == bs && ja.w > bj)) { bs = sa.w; bj = ja.w; bp = r + 3; }
+    if (sb.x < bs || (sb.x == bs && jb.x > bj)) { bs = sb.x; bj = jb.x; bp = r + 4; }
+    if (sb.y < bs || (sb.y == bs && jb.y > bj)) { bs = sb.y; bj = jb.y; bp = r + 5; }
+    if (sb.z < bs || (sb.z == bs && jb.z > bj)) { bs = sb.z; bj = jb.z; bp = r + 6; }
+    if (sb.w < bs || (sb.w == bs && jb.w > bj)) { bs = sb.w; bj = jb.w; bp = r + 7; }
   }
-  *wv = bs;
-  *wi = bj;
-  *wp = bp;
+  ws = bs;
+  wj = bj;
+  wp = bp;
 }
 
 template <int DP, int QW, int NBUF>
@@ -391,6 +401,8 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
           if (hit && half == h) {
             float tcur = lwv[q];
             int tcur_i = lwi[q];
+            int wslot = lwp[q];
+            bool changed = false;
             // a candidate can enter only if its raw score reaches the tile bound fth (fth is at
             // most the list's worst score times the smallest candidate norm of the tile), so the
             // norm and index of a candidate are read only when that test passes
@@ -405,12 +417,16 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
                   const int jp = tperm[cl];
                   const float sc = a * iv;
                   if (iv > 0.0f && jp != qi && better<float>(sc, jp, tcur, tcur_i)) {
-                    list_replace_worst(ls, li, KPP, lwv + q, lwi + q, lwp + q, sc, jp);
-                    tcur = lwv[q];
-                    tcur_i = lwi[q];
+                    list_replace_worst(ls, li, KPP, sc, jp, tcur, tcur_i, wslot);
+                    changed = true;
                   }
                 }
               }
+            }
+            if (changed) {
+              lwv[q] = tcur;
+              lwi[q] = tcur_i;
+              lwp[q] = wslot;
             }
           }
           // the two halves of the wave update the same lists in turn.  LDS operations of one

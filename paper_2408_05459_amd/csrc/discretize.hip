@@ -36,13 +36,13 @@ __global__ __launch_bounds__(256) void disc_pass_kernel(const T* __restrict__ Q,
                                                         unsigned int* __restrict__ cg,
                                                         const DiscState* __restrict__ st) {
   if (st->done) return;
-  __shared__ T Rs[KM][KM];
+  __shared__ __align__(16) T Rs[KM][KM];   // Rs[j][c] = R[c][j] (zero outside k x k)
   __shared__ unsigned long long Ss[KM * KM];
   __shared__ unsigned int cs[KM];
   const int tid = threadIdx.x;
   for (int e = tid; e < KM * KM; e += 256) {
-    const int i = e / KM, j = e % KM;
-    Rs[i][j] = (i < k && j < k) ? R[i * k + j] : (T)0;
+    const int j = e / KM, c = e % KM;
+    Rs[j][c] = (c < k && j < k) ? R[c * k + j] : (T)0;
     Ss[e] = 0ull;
   }
   if (tid < KM) cs[tid] = 0u;
@@ -63,12 +63,24 @@ __global__ __launch_bounds__(256) void disc_pass_kernel(const T* __restrict__ Q,
     }
     int best = 0;
     T bv = (T)0;
+    constexpr int VW = 16 / sizeof(T);   // R entries per 16-byte LDS read
 #pragma unroll
     for (int j = 0; j < KM; j++) {
       if (j < k) {
         T t = (T)0;
 #pragma unroll
-        for (int c = 0; c < KM; c++) t = fma(q[c], Rs[c][j], t);
+        for (int c = 0; c < KM; c += VW) {
+          T r[VW];
+          if constexpr (VW == 4) {
+            const float4 v = *(const float4*)&Rs[j][c];
+            r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
+          } else {
+            const double2 v = *(const double2*)&Rs[j][c];
+            r[0] = v.x; r[1] = v.y;
+          }
+#pragma unroll
+          for (int u = 0; u < VW; u++) t = fma(q[c + u], r[u], t);
+        }
         if (j == 0 || t > bv) {
           bv = t;
           best = j;
@@ -141,7 +153,7 @@ __device__ void complete_null_cols(double (*B)[KM + 1], int k, const int* isnull
 template <typename T, int KM>
 __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __restrict__ Sg, unsigned int* __restrict__ cg,
                                                        int k, int64_t n, double* __restrict__ Rd, T* __restrict__ Rt,
-                                                       DiscState* __restrict__ st) {
+                                                       double* __restrict__ Vg, DiscState* __restrict__ st) {
   if (st->done) return;
   __shared__ double A[KM][KM + 1];   // A[j][i] = column j of M (then of M V)
   __shared__ double V[KM][KM + 1];   // V[j][i] = column j of V
@@ -160,6 +172,28 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
     }
     A[j][c] = v;
     V[j][c] = (c == j && c < k) ? 1.0 : 0.0;
+  }
+  // After the first step of a call, the rotation starts from the previous step's V (M changes
+  // little between steps, so few sweeps remain): A <- M V, one row of M per thread.
+  const bool warm = st->iters > 0;
+  if (warm) {
+    for (int e = tid; e < KM * KM; e += 256) {
+      const int j = e / KM, c = e % KM;
+      V[j][c] = (j < k && c < k) ? Vg[j * KM + c] : ((j == c) ? 1.0 : 0.0);
+    }
+  }
+  __syncthreads();
+  if (warm && tid < k) {
+    double m[KM];
+#pragma unroll
+    for (int i = 0; i < KM; i++) m[i] = (i < k) ? A[i][tid] : 0.0;
+    for (int j = 0; j < k; j++) {
+      double a = 0.0;
+#pragma unroll
+      for (int i = 0; i < KM; i++)
+        if (i < k) a += m[i] * V[j][i];
+      A[j][tid] = a;
+    }
   }
   __syncthreads();
   for (int e = tid; e < k * k; e += 256) Sg[e] = 0ull;
@@ -245,7 +279,8 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
     complete_null_cols<KM>(V, k, isnull, tid);
   }
   __syncthreads();
-  // R = V U^T
+  // keep V for the next step; R = V U^T
+  for (int e = tid; e < k * k; e += 256) Vg[(e / k) * KM + (e % k)] = V[e / k][e % k];
   for (int e = tid; e < k * k; e += 256) {
     const int a = e / k, b = e % k;
     double s = 0.0;
@@ -294,6 +329,8 @@ ancka_status disc_launch(ancka_ctx* ctx, const T* Q, int64_t n, int k, int64_t l
   ST_TRY(ws_get_t(ctx, "disc_S", 64 * 64, &Sg));
   ST_TRY(ws_get_t(ctx, "disc_c", 64, &cg));
   ST_TRY(ws_get_t(ctx, "disc_st", 1, &st));
+  double* Vg = nullptr;
+  ST_TRY(ws_get_t(ctx, "disc_V", 64 * 64, &Vg));
   disc_init_kernel<T><<<16, 256, 0, ctx->stream>>>(k, Rd, Rt, st, Sg, cg);
   LAUNCH_CHECK(ctx);
   const unsigned grid = (unsigned)cdiv(n, 256);
@@ -301,7 +338,7 @@ ancka_status disc_launch(ancka_ctx* ctx, const T* Q, int64_t n, int k, int64_t l
   for (int it = 0; it < max_iter; it++) {
     disc_pass_kernel<T, KM><<<grid, 256, 0, ctx->stream>>>(Q, n, k, ldq, Rt, labels, Sg, cg, st);
     LAUNCH_CHECK(ctx);
-    disc_svd_kernel<T, KM><<<1, 256, 0, ctx->stream>>>(Sg, cg, k, n, Rd, Rt, st);
+    disc_svd_kernel<T, KM><<<1, 256, 0, ctx->stream>>>(Sg, cg, k, n, Rd, Rt, Vg, st);
     LAUNCH_CHECK(ctx);
     if ((it % 4) == 3 || it == max_iter - 1) {
       HIP_TRY(ctx, hipMemcpyAsync(&hs, st, sizeof(DiscState), hipMemcpyDeviceToHost, ctx->stream));

@@ -249,7 +249,7 @@ def main():
     op = lib.build_operator(s, nidx, nsim, prm.K, prm.beta, prm.q_dtype)
     oinfo = op.info()
     kp = net.k + 1
-    ld = kp + (-kp) % 4
+    ld = ((kp * 4 + 127) // 128) * 32 if kp * 4 > 128 else max(4, 1 << (kp - 1).bit_length())   # as the library pads
     Q = torch.randn((n, ld), dtype=torch.float32, device="cuda")
     for _ in range(3):
         op.apply(Q)

@@ -183,9 +183,20 @@ __global__ void warm_argmax_kernel(const float* __restrict__ Z, int64_t n, int k
 }
 
 unsigned nb256(int64_t c) { return (unsigned)cdiv(c > 0 ? c : 1, 256); }
+// Leading dimension of the n x cols blocks the sparse products gather rows from: rows of at most
+// 128 bytes are padded to a power of two of bytes (16..128) and longer rows to a multiple of 128
+// bytes, so a row gather never straddles more cache lines than its size requires.
 int64_t pad_ld(int cols, int dtype) {
-  const int vw = dtype == ANCKA_F64 ? 2 : 4;
-  return (cols + vw - 1) / vw * vw;
+  const int es = dtype == ANCKA_F64 ? 8 : 4;
+  int64_t bytes = (int64_t)cols * es;
+  if (bytes <= 128) {
+    int64_t p2 = 16;
+    while (p2 < bytes) p2 *= 2;
+    bytes = p2;
+  } else {
+    bytes = (bytes + 127) / 128 * 128;
+  }
+  return bytes / es;
 }
 
 template <typename T>
@@ -367,6 +378,7 @@ ancka_status cluster_loop(ancka_ctx* ctx, const ancka_op* op, const ancka_params
   ST_TRY(ws_get(ctx, "cl_Qn", (size_t)n * ldq * es, &Qn));
   ST_TRY(ws_get(ctx, "cl_Z", (size_t)n * ldq * es, &Z));
   // padding columns stay zero through every product (they are never written by the QR)
+  ST_TRY(fill_zero(ctx, Q, (size_t)n * ldq * es));
   ST_TRY(fill_zero(ctx, Qn, (size_t)n * ldq * es));
   ST_TRY(fill_zero(ctx, Z, (size_t)n * ldq * es));
   ST_TRY(ws_get_t(ctx, "cl_dq2", 2, &dq2));

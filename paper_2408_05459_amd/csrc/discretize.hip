@@ -153,7 +153,7 @@ __device__ void complete_null_cols(double (*B)[KM + 1], int k, const int* isnull
 template <typename T, int KM>
 __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __restrict__ Sg, unsigned int* __restrict__ cg,
                                                        int k, int64_t n, double* __restrict__ Rd, T* __restrict__ Rt,
-                                                       double* __restrict__ Vg, DiscState* __restrict__ st) {
+                                                       DiscState* __restrict__ st) {
   if (st->done) return;
   __shared__ double A[KM][KM + 1];   // A[j][i] = column j of M (then of M V)
   __shared__ double V[KM][KM + 1];   // V[j][i] = column j of V
@@ -172,28 +172,6 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
     }
     A[j][c] = v;
     V[j][c] = (c == j && c < k) ? 1.0 : 0.0;
-  }
-  // After the first step of a call, the rotation starts from the previous step's V (M changes
-  // little between steps, so few sweeps remain): A <- M V, one row of M per thread.
-  const bool warm = st->iters > 0;
-  if (warm) {
-    for (int e = tid; e < KM * KM; e += 256) {
-      const int j = e / KM, c = e % KM;
-      V[j][c] = (j < k && c < k) ? Vg[j * KM + c] : ((j == c) ? 1.0 : 0.0);
-    }
-  }
-  __syncthreads();
-  if (warm && tid < k) {
-    double m[KM];
-#pragma unroll
-    for (int i = 0; i < KM; i++) m[i] = (i < k) ? A[i][tid] : 0.0;
-    for (int j = 0; j < k; j++) {
-      double a = 0.0;
-#pragma unroll
-      for (int i = 0; i < KM; i++)
-        if (i < k) a += m[i] * V[j][i];
-      A[j][tid] = a;
-    }
   }
   __syncthreads();
   for (int e = tid; e < k * k; e += 256) Sg[e] = 0ull;
@@ -279,8 +257,7 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
     complete_null_cols<KM>(V, k, isnull, tid);
   }
   __syncthreads();
-  // keep V for the next step; R = V U^T
-  for (int e = tid; e < k * k; e += 256) Vg[(e / k) * KM + (e % k)] = V[e / k][e % k];
+  // R = V U^T
   for (int e = tid; e < k * k; e += 256) {
     const int a = e / k, b = e % k;
     double s = 0.0;
@@ -329,8 +306,6 @@ ancka_status disc_launch(ancka_ctx* ctx, const T* Q, int64_t n, int k, int64_t l
   ST_TRY(ws_get_t(ctx, "disc_S", 64 * 64, &Sg));
   ST_TRY(ws_get_t(ctx, "disc_c", 64, &cg));
   ST_TRY(ws_get_t(ctx, "disc_st", 1, &st));
-  double* Vg = nullptr;
-  ST_TRY(ws_get_t(ctx, "disc_V", 64 * 64, &Vg));
   disc_init_kernel<T><<<16, 256, 0, ctx->stream>>>(k, Rd, Rt, st, Sg, cg);
   LAUNCH_CHECK(ctx);
   const unsigned grid = (unsigned)cdiv(n, 256);
@@ -338,7 +313,7 @@ ancka_status disc_launch(ancka_ctx* ctx, const T* Q, int64_t n, int k, int64_t l
   for (int it = 0; it < max_iter; it++) {
     disc_pass_kernel<T, KM><<<grid, 256, 0, ctx->stream>>>(Q, n, k, ldq, Rt, labels, Sg, cg, st);
     LAUNCH_CHECK(ctx);
-    disc_svd_kernel<T, KM><<<1, 256, 0, ctx->stream>>>(Sg, cg, k, n, Rd, Rt, Vg, st);
+    disc_svd_kernel<T, KM><<<1, 256, 0, ctx->stream>>>(Sg, cg, k, n, Rd, Rt, st);
     LAUNCH_CHECK(ctx);
     if ((it % 4) == 3 || it == max_iter - 1) {
       HIP_TRY(ctx, hipMemcpyAsync(&hs, st, sizeof(DiscState), hipMemcpyDeviceToHost, ctx->stream));

@@ -392,6 +392,8 @@ ancka_status initial_block(ancka_ctx* ctx, const ancka_op* op, const int32_t* la
     if (last >= 0) hfill[last + 1] = 1;
   }
   HIP_TRY(ctx, hipMemcpyAsync(fill, hfill.data(), sizeof(int) * 72, hipMemcpyHostToDevice, ctx->stream));
+  // the host array dies with this call: the copy must have read it before returning
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   void* Z = nullptr;
   const size_t es = op->dtype == ANCKA_F64 ? 8 : 4;
   ST_TRY(ws_get(ctx, "ib_Z", (size_t)n * ldq * es, &Z));

@@ -242,6 +242,7 @@ def test_cluster_deterministic(lib):
     s, keep = lib.network(net)
     params = lib.default_params(k=net.k, K=prm.K, knn_mode=prm.knn_mode, q_dtype=prm.q_dtype)
     a, ia = lib.cluster(s, params)
-    b, ib = lib.cluster(s, params)
-    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
-    assert ia["best_phi"] == ib["best_phi"] and ia["trace"] == ib["trace"]
+    for _ in range(2):
+        b, ib = lib.cluster(s, params)
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+        assert ia["best_phi"] == ib["best_phi"] and ia["trace"] == ib["trace"]

@@ -582,14 +582,86 @@ __global__ void tile_min_sorted_kernel(const float* __restrict__ invs, int64_t n
   out[t] = m * (1.0f - 4e-7f);
 }
 
-// first tile of each workgroup's scan: the tile holding the first row of the cell of its first
-// query (sorted keys carry the cell in bits 32..)
-__global__ void wg_start_kernel(const uint64_t* __restrict__ keys, int64_t n, int qb, int64_t nwg,
+// cs[c] = first sorted position of cell c (keys sorted by cell << 32 | norm), cs[NPIV] = n
+__global__ void cell_starts_kernel(const uint64_t* __restrict__ keys, int64_t n, int64_t* __restrict__ cs) {
+  const int c = threadIdx.x;
+  if (c > NPIV) return;
+  const uint64_t target = (uint64_t)c << 32;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (keys[mid] < target) lo = mid + 1;
+    else hi = mid;
+  }
+  cs[c] = lo;
+}
+
+// Second level of the scan order: each row of cell c (sorted positions cs[c] .. cs[c+1]) takes the
+// most similar of NPIV sub-pivots, the rows at evenly spaced positions of its cell (ties to the
+// smaller sub-pivot).  key2 = c << 6 | sub.  Block (x, c) handles 256 consecutive rows of cell c.
+template <typename TX>
+__global__ __launch_bounds__(256) void subcell_assign_kernel(const TX* __restrict__ X, int64_t d, int64_t ldx,
+                                                             const float* __restrict__ invn,
+                                                             const int64_t* __restrict__ cs,
+                                                             const uint64_t* __restrict__ order,
+                                                             uint64_t* __restrict__ key2) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int c = blockIdx.y;
+  const int64_t c0 = cs[c], size = cs[c + 1] - c0;
+  const int64_t p0 = c0 + (int64_t)blockIdx.x * 256;
+  if (p0 >= c0 + size) return;
+  const int dp = (int)((d + 7) / 8 * 8);
+  uint16_t* P = (uint16_t*)smem;            // [NPIV][dp]
+  float* pinv = (float*)(P + NPIV * dp);    // [NPIV]
+  for (int e = threadIdx.x; e < NPIV * dp; e += 256) {
+    const int s = e / dp, col = e % dp;
+    const int64_t row = (int64_t)order[c0 + (int64_t)s * size / NPIV];
+    P[e] = (col < d) ? f32_to_bf16_rne((float)load_as_double<TX>(X, row * ldx + col)) : (uint16_t)0;
+  }
+  if (threadIdx.x < NPIV) pinv[threadIdx.x] = invn[order[c0 + (int64_t)threadIdx.x * size / NPIV]];
+  __syncthreads();
+  const int64_t p = p0 + threadIdx.x;
+  if (p >= c0 + size) return;
+  const TX* xr = X + (int64_t)order[p] * ldx;
+  float acc[NPIV];
+#pragma unroll
+  for (int s = 0; s < NPIV; s++) acc[s] = 0.0f;
+  for (int col0 = 0; col0 < dp; col0 += 8) {
+    float xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) xv[u] = (col0 + u < d) ? (float)load_as_double<TX>(xr, col0 + u) : 0.0f;
+#pragma unroll
+    for (int s = 0; s < NPIV; s++) {
+      const uint4 pv = *(const uint4*)(P + s * dp + col0);
+      const uint32_t w[4] = {pv.x, pv.y, pv.z, pv.w};
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        acc[s] = fmaf(xv[2 * u], __uint_as_float(w[u] << 16), acc[s]);
+        acc[s] = fmaf(xv[2 * u + 1], __uint_as_float(w[u] & 0xffff0000u), acc[s]);
+      }
+    }
+  }
+  int best = 0;
+  float bv = acc[0] * pinv[0];
+#pragma unroll
+  for (int s = 1; s < NPIV; s++) {
+    const float v = acc[s] * pinv[s];
+    if (v > bv) {
+      bv = v;
+      best = s;
+    }
+  }
+  key2[p] = ((uint64_t)c << 6) | (uint64_t)best;
+}
+
+// first tile of each workgroup's scan: the tile holding the first row of the group (cell, or
+// cell and sub-cell) of its first query; the group is the sorted key shifted right by `shift`
+__global__ void wg_start_kernel(const uint64_t* __restrict__ keys, int64_t n, int qb, int64_t nwg, int shift,
                                 int32_t* __restrict__ start) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nwg) return;
-  const uint64_t cell = keys[b * qb] >> 32;
-  const uint64_t target = cell << 32;
+  const uint64_t cell = keys[b * qb] >> shift;
+  const uint64_t target = cell << shift;
   int64_t lo = 0, hi = n;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
@@ -894,6 +966,7 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
       int64_t hp[NPIV];
       for (int p = 0; p < NPIV; p++) hp[p] = (int64_t)((double)p * (double)n / NPIV);
       HIP_TRY(ctx, hipMemcpyAsync(piv, hp, sizeof(hp), hipMemcpyHostToDevice, ctx->stream));
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));   // hp is a stack array
       const size_t csm = (size_t)NPIV * ((d + 7) / 8 * 8) * 2 + NPIV * 4;
       static bool cattr = false;
       if (!cattr) {
@@ -905,12 +978,34 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
           (const uint16_t*)(const void*)X, n, d, ldx, invn, piv, keys, nrm, order);
       LAUNCH_CHECK(ctx);
       ST_TRY(radix_sort_u64(ctx, keys, order, n, 40));
+      // second level: rows of a cell grouped by the nearest of NPIV sub-pivots of that cell, the
+      // norm order kept inside a group (stable sort on the 12-bit group key); a workgroup starts
+      // its scan at its own group, whose rows are the likeliest neighbours of its queries
+      int64_t* cstart = nullptr;
+      ST_TRY(ws_get_t(ctx, "knn_cstart", NPIV + 1, &cstart));
+      cell_starts_kernel<<<1, 128, 0, ctx->stream>>>(keys, n, cstart);
+      LAUNCH_CHECK(ctx);
+      int64_t hcs[NPIV + 1];
+      HIP_TRY(ctx, hipMemcpyAsync(hcs, cstart, sizeof(hcs), hipMemcpyDeviceToHost, ctx->stream));
+      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      int64_t maxc = 1;
+      for (int c = 0; c < NPIV; c++) maxc = (hcs[c + 1] - hcs[c]) > maxc ? (hcs[c + 1] - hcs[c]) : maxc;
+      static bool sattr = false;
+      if (!sattr) {
+        HIP_TRY(ctx, hipFuncSetAttribute((const void*)subcell_assign_kernel<uint16_t>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        sattr = true;
+      }
+      subcell_assign_kernel<uint16_t><<<dim3((unsigned)cdiv(maxc, 256), NPIV), 256, csm, ctx->stream>>>(
+          (const uint16_t*)(const void*)X, d, ldx, invn, cstart, order, keys);
+      LAUNCH_CHECK(ctx);
+      ST_TRY(radix_sort_u64(ctx, keys, order, n, 12));
       gather_sorted_kernel<<<(unsigned)cdiv(npad, 4), 256, 0, ctx->stream>>>((const uint16_t*)(const void*)X, n, npad,
                                                                              d, ldx, order, invn, DP, Xs, invs, perm);
       LAUNCH_CHECK(ctx);
       tile_min_sorted_kernel<<<(unsigned)cdiv(nt, 256), 256, 0, ctx->stream>>>(invs, n, BT_C, tmin, nt);
       LAUNCH_CHECK(ctx);
-      wg_start_kernel<<<(unsigned)cdiv(nwg, 256), 256, 0, ctx->stream>>>(keys, n, QB, nwg, wgs);
+      wg_start_kernel<<<(unsigned)cdiv(nwg, 256), 256, 0, ctx->stream>>>(keys, n, QB, nwg, 0, wgs);
       LAUNCH_CHECK(ctx);
       HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
       ST_TRY(run_bf16(ctx, DP, Xs, n, invs, perm, tmin, wgs, KP, cidx, csim));
@@ -952,6 +1047,7 @@ ancka_status cell_order_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d,
   int64_t hp[NPIV];
   for (int p = 0; p < NPIV; p++) hp[p] = (int64_t)((double)p * (double)n / NPIV);
   HIP_TRY(ctx, hipMemcpyAsync(piv, hp, sizeof(hp), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));   // hp is a stack array
   const size_t csm = (size_t)NPIV * ((d + 7) / 8 * 8) * 2 + NPIV * 4;
   if (csm > 160 * 1024) return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "cell order: d too large");
   static bool cattr = false;

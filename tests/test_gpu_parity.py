@@ -246,3 +246,20 @@ def test_cluster_deterministic(lib):
         b, ib = lib.cluster(s, params)
         assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
         assert ia["best_phi"] == ib["best_phi"] and ia["trace"] == ib["trace"]
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_cluster_op_matches_cluster(lib, cfg):
+    """The method from a separately built operator (ancka_cluster_op) equals the whole call."""
+    net, prm, op, ki, ks = workload(cfg)
+    s, keep = lib.network(net)
+    params = lib.default_params(k=net.k, K=prm.K, alpha=prm.alpha, beta=prm.beta, gamma=prm.gamma, tau=prm.tau,
+                                T_i=prm.T_i, T_a=prm.T_a, eps_q=prm.eps_q, knn_mode=prm.knn_mode,
+                                q_dtype=prm.q_dtype)
+    a, ia = lib.cluster(s, params)
+    idx, sim, _ = lib.knn(keep[-1], prm.K, prm.knn_mode)
+    gop = lib.build_operator(s, idx, sim, prm.K, prm.beta, prm.q_dtype)
+    b, ib = lib.cluster(None, params, op=gop)
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    assert ia["best_phi"] == ib["best_phi"] and ia["trace"] == ib["trace"]
+    assert ib["phase_ms"]["knn"] == 0.0 and ib["phase_ms"]["operator"] == 0.0

@@ -96,8 +96,14 @@ typedef struct {
   int64_t zero_rows;         /* attribute rows that are all zero */
   int64_t uncertified_rows;  /* rows whose 2K candidate list could not prove the top-K */
   int64_t recomputed_rows;   /* rows recomputed exactly (= uncertified_rows) */
-  double tile_ms;            /* duration of the similarity-tile + top-K kernel (HIP events on the stream) */
+  double tile_ms;            /* duration of the similarity-tile + top-K phase (HIP events on the stream);
+                                for BF16_RESCORE: window pass, symmetric pass and list merge */
   double total_ms;           /* duration of the whole ancka_knn call on the stream */
+  double sym_ms;             /* BF16_RESCORE: duration of the symmetric-pass kernel (0 if not run) */
+  int64_t sym_pairs;         /* unordered row pairs the symmetric pass scores (padding rows included) */
+  int64_t handed_over;       /* candidate pairs the symmetric pass handed to other rows' lists */
+  int32_t window;            /* half-width, in blocks of rows, of the window pass; -1: whole scan */
+  int32_t rescanned;         /* 1 if the hand-over buffer overflowed and the scan was redone whole */
 } ancka_knn_stats;
 
 enum { ANCKA_PHASE_KNN = 0, ANCKA_PHASE_OPERATOR = 1, ANCKA_PHASE_INIT = 2, ANCKA_PHASE_ITER = 3,

@@ -44,7 +44,9 @@ class ancka_params(C.Structure):
 
 class ancka_knn_stats(C.Structure):
     _fields_ = [("zero_rows", C.c_int64), ("uncertified_rows", C.c_int64), ("recomputed_rows", C.c_int64),
-                ("tile_ms", C.c_double), ("total_ms", C.c_double)]
+                ("tile_ms", C.c_double), ("total_ms", C.c_double), ("sym_ms", C.c_double),
+                ("sym_pairs", C.c_int64), ("handed_over", C.c_int64), ("window", C.c_int32),
+                ("rescanned", C.c_int32)]
 
 
 class ancka_report(C.Structure):
@@ -263,6 +265,9 @@ class Lib:
             "phase_ms": {PHASES[i]: rep.phase_ms[i] for i in range(ANCKA_NPHASES)},
             "knn_zero_rows": rep.knn.zero_rows, "knn_uncertified_rows": rep.knn.uncertified_rows,
             "knn_tile_ms": rep.knn.tile_ms, "knn_total_ms": rep.knn.total_ms,
+            "knn_sym_ms": rep.knn.sym_ms, "knn_sym_pairs": rep.knn.sym_pairs,
+            "knn_handed_over": rep.knn.handed_over, "knn_window": rep.knn.window,
+            "knn_rescanned": rep.knn.rescanned,
             "disc_iters_total": rep.disc_iters_total,
         }
         return labels, info

@@ -13,6 +13,9 @@
 #include <cfloat>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
+#include <vector>
+#include <algorithm>
 
 #include "common.h"
 
@@ -189,13 +192,22 @@ __global__ __launch_bounds__(256) void knn_vector_kernel(const TX* __restrict__ 
 }
 
 // ---- BF16 MFMA tiles ------------------------------------------------------------------------
-// Scan order.  Rows are grouped into coarse cells (the most similar of NPIV pivot rows) and,
-// inside a cell, ordered by norm; queries and candidates share this order (a bf16 copy Xs).  A
-// workgroup owns 4*QW consecutive queries -- mostly one cell -- and scans every candidate tile
-// once, starting with the first tile of its own cell and wrapping around.  The order changes
-// nothing in the result (every candidate is scored; lists are ordered by the (similarity,
-// index) key) but it makes each query's running threshold nearly final after its own cell, so
-// later tiles seldom reach the insertion path.
+// Scan order.  Rows are grouped into coarse cells (the most similar of NPIV pivot rows) and
+// sub-cells; queries and candidates share this order (a bf16 copy Xs, padded to whole blocks of
+// QB = 4*QW rows).  Workgroup I owns block I of QB consecutive queries.
+// Two passes cover every unordered pair of rows.
+//  Window pass: block I scans the tiles of blocks I-w .. I+w (cyclically), starting at its own
+//    sub-cell; the most similar rows lie there, so each list ends close to its final state.
+//  Symmetric pass: block I scans blocks I+w+1 .. I+h (h = half the ring; for an even block count
+//    the opposite block is scanned only from the lower half), so each remaining pair of blocks
+//    meets once.  A tile score a = x_i.x_j serves both rows: the query side updates the lists
+//    of block I in LDS as in the window pass; on the candidate side, a pair whose score reaches
+//    the candidate row's threshold after the window pass (the worst entry of its list then)
+//    is handed over through a global buffer and merged into that row's list afterwards.  The
+//    candidate-side test is a necessary condition for entering the final list, so the merged
+//    lists equal those of a full scan of all pairs.
+// With w >= the ring's half the window pass is the whole scan and the symmetric pass is skipped.
+// The order changes nothing in the result (lists are ordered by the (similarity, index) key).
 // Tiles.  Wave w holds its QW queries as MFMA B operands in registers for the whole kernel;
 // 64-row candidate tiles (two 32-row A blocks) stream through double-buffered LDS.
 // Epilogue.  A lane holds 16 candidates of one query per (A block, B block).  The maximum raw
@@ -242,14 +254,38 @@ __device__ __forceinline__ void list_replace_worst(float* ls, int* li, int kpp, 
   wp = bp;
 }
 
-template <int DP, int QW, int NBUF>
-__global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
-    const uint16_t* __restrict__ Xs, int64_t n, const float* __restrict__ invs, const int32_t* __restrict__ perm,
-    const float* __restrict__ tile_min, const int32_t* __restrict__ wg_start, int KP, int32_t* __restrict__ cand_idx,
-    float* __restrict__ cand_sim) {
+// Arguments of both passes.  Lists are kept per sorted row p in [0, npad): KP entries sorted
+// best first, original row indices (INT_MAX: empty slot) and raw scores x_p.x_j / |x_j| (the
+// cosine times |x_p|, which orders a row's candidates like the cosine).
+struct ScanArgs {
+  const uint16_t* Xs;        // [npad][DP] bf16 rows in scan order, zero padded
+  const float* invs;         // [npad] 1/|x|, 0 for zero and padding rows
+  const int32_t* perm;       // [npad] original index, -1 for padding rows
+  const float* tile_min;     // [ntp] smallest norm of a non-zero row of each tile (+inf if none)
+  const int32_t* wg_start;   // [nwg] first tile of each block's own sub-cell
+  int64_t nwg;               // blocks of QB rows (workgroups)
+  int64_t ntp;               // tiles in the padded ring, nwg * QB / BT_C
+  int w;                     // -1: the window is the whole ring (no symmetric pass); else >= 0
+  const int32_t* wlo;        // [nwg] window of block I: blocks wlo[I] .. whi[I] (unwrapped, taken
+  const int32_t* whi;        //   mod nwg); wlo <= I <= whi, and J in I's window iff I in J's
+  int KP;                    // list length
+  int32_t* lidx;             // [npad][KP] lists (written by the window pass, updated in place)
+  float* lsim;               // [npad][KP]
+  float* colthr;             // [npad] candidate-side threshold: the list's worst raw score after
+                             // the window pass (-inf if not full; +inf for zero and padding rows)
+  const float* tile_thr;     // [ntp] smallest colthr of each tile (symmetric pass)
+  uint64_t* hkey;            // hand-over buffer: sorted row that receives the candidate
+  uint64_t* hval;            //   (original index of the candidate << 32) | raw score bits
+  unsigned long long* hcount;  // entries produced (may exceed hcap: then the buffer overflowed)
+  int64_t hcap;
+};
+
+template <int DP, int QW, int NBUF, bool SYM>
+__global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(ScanArgs args) {
   constexpr int KS = DP / 16;           // MFMA k-steps
   constexpr int NQB = QW / 32;          // query blocks per wave
   constexpr int QB = 4 * QW;            // queries per workgroup
+  constexpr int TPB = QB / BT_C;        // tiles per block
   constexpr int LDR = DP + 8;           // LDS row stride in bf16 (16-byte pad)
   constexpr int CHUNKS = BT_C * DP / 8; // 16-byte chunks per tile
   constexpr int CPT = CHUNKS / 256;     // chunks per thread
@@ -260,35 +296,59 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
   uint16_t* tileb = (uint16_t*)smem;                         // [NBUF][BT_C][LDR]
   float* tinv = (float*)(tileb + NBUF * BT_C * LDR);         // [NBUF][BT_C]
   int* tperm = (int*)(tinv + NBUF * BT_C);                   // [NBUF][BT_C]
-  float* tmn = (float*)(tperm + NBUF * BT_C);                // [NBUF] (padded to 4)
+  float* tmn = (float*)(tperm + NBUF * BT_C);                // [NBUF] smallest norm, [2 + NBUF] tile_thr
+  const int KP = args.KP;
   const int KPP = (KP + 3) & ~3;                             // list slots per query
   float* lsim = tmn + 4;                                     // [QB][KPP]
   int* lidx = (int*)(lsim + QB * KPP);                       // [QB][KPP]
   float* lwv = (float*)(lidx + QB * KPP);                    // [QB] worst score of each list
   int* lwi = (int*)(lwv + QB);                               // [QB] its index
   int* lwp = lwi + QB;                                       // [QB] its slot
+  float* tthr = (float*)(lwp + QB);                          // [NBUF][BT_C] colthr (symmetric pass)
 
   const int tid = threadIdx.x;
   const int wave = tid / ANCKA_WAVE;
   const int lane = tid % ANCKA_WAVE;
   const int l32 = lane % 32;
   const int half = lane / 32;
-  const int64_t q0 = (int64_t)blockIdx.x * QB;
+  const int64_t blk = blockIdx.x;
+  const int64_t q0 = blk * QB;
 
-  for (int e = tid; e < QB * KPP; e += 256) {
-    const bool pad = (e % KPP) >= KP;
-    lsim[e] = pad ? INFINITY : -INFINITY;
-    lidx[e] = pad ? -1 : INT_MAX;
+  if (!SYM) {
+    for (int e = tid; e < QB * KPP; e += 256) {
+      const bool pad = (e % KPP) >= KP;
+      lsim[e] = pad ? INFINITY : -INFINITY;
+      lidx[e] = pad ? -1 : INT_MAX;
+    }
+    for (int q = tid; q < QB; q += 256) {
+      lwv[q] = -INFINITY;
+      lwi[q] = INT_MAX;
+      lwp[q] = 0;
+    }
+  } else {
+    // the window pass's lists (sorted best first): the worst entry is the first empty slot, or
+    // the last slot of a full list
+    for (int e = tid; e < QB * KPP; e += 256) {
+      const int q = e / KPP, r = e % KPP;
+      const int64_t g = (q0 + q) * KP + r;
+      lsim[e] = r < KP ? args.lsim[g] : INFINITY;
+      lidx[e] = r < KP ? args.lidx[g] : -1;
+    }
+    __syncthreads();
+    for (int q = tid; q < QB; q += 256) {
+      int r = 0;
+      while (r < KP - 1 && lidx[q * KPP + r] != INT_MAX) r++;
+      lwv[q] = lsim[q * KPP + r];
+      lwi[q] = lidx[q * KPP + r];
+      lwp[q] = r;
+    }
   }
-  for (int q = tid; q < QB; q += 256) {
-    lwv[q] = -INFINITY;
-    lwi[q] = INT_MAX;
-    lwp[q] = 0;
-  }
+  __syncthreads();
 
   // query fragments: lane holds 8 bf16 of query row (l32) at k = ks*16 + half*8
   bf16x8 bq[NQB][KS];
   float thr[NQB];
+  float colq[NQB];   // symmetric pass: 1/|x_i| of the lane's query (0: the query takes no part)
   int qloc[NQB];
   int qorig[NQB];
   // Xs, invs and perm are padded with zero rows (invs 0, perm -1) to whole workgroups, so no
@@ -298,17 +358,47 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
   for (int qb = 0; qb < NQB; qb++) {
     qloc[qb] = wave * QW + qb * 32 + l32;
     const int64_t qs = q0 + qloc[qb];
-    qorig[qb] = perm[qs];
-    thr[qb] = invs[qs] > 0.0f ? -INFINITY : INFINITY;
+    qorig[qb] = args.perm[qs];
+    const float iq = args.invs[qs];
+    thr[qb] = iq > 0.0f ? (SYM ? lwv[qloc[qb]] : -INFINITY) : INFINITY;
+    colq[qb] = iq;
 #pragma unroll
     for (int ks = 0; ks < KS; ks++) {
-      const uint4 v = *(const uint4*)(Xs + qs * DP + ks * 16 + half * 8);
+      const uint4 v = *(const uint4*)(args.Xs + qs * DP + ks * 16 + half * 8);
       bq[qb][ks] = __builtin_bit_cast(bf16x8, v);
     }
   }
 
-  const int64_t ntiles = cdiv(n, BT_C);
-  const int64_t t0 = wg_start[blockIdx.x];
+  // this workgroup's scan: L tiles of the ring starting at tile ws, beginning at offset s0
+  const int64_t ntp = args.ntp;
+  int64_t ws, L, s0;
+  if (!SYM) {
+    if (args.w < 0) {
+      ws = 0;
+      L = ntp;
+      s0 = args.wg_start[blk];
+    } else {
+      const int64_t lo = args.wlo[blk], hi = args.whi[blk];
+      int64_t b0 = lo;
+      if (b0 < 0) b0 += args.nwg;
+      ws = b0 * TPB;
+      L = (hi - lo + 1) * TPB;
+      s0 = args.wg_start[blk] - ws;
+      if (s0 < 0) s0 += ntp;
+      if (s0 >= L) s0 = (blk - lo) * TPB;
+    }
+  } else {
+    const int64_t hb = (args.nwg % 2 == 0 && blk >= args.nwg / 2) ? args.nwg / 2 - 1 : args.nwg / 2;
+    const int64_t hi = args.whi[blk];
+    ws = ((hi + 1) % args.nwg) * TPB;
+    L = blk + hb > hi ? (blk + hb - hi) * TPB : 0;
+    s0 = 0;
+  }
+  const int64_t ntiles = L;
+  const uint16_t* __restrict__ Xs = args.Xs;
+  const float* __restrict__ invs = args.invs;
+  const int32_t* __restrict__ perm = args.perm;
+  const float* __restrict__ tile_min = args.tile_min;
   // this thread's 16-byte chunks of a tile: element offsets in global memory and in LDS
   int goff[CPT], loff[CPT];
 #pragma unroll
@@ -322,18 +412,31 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
   float pre_inv = 0.0f;
   int pre_perm = -1;
   float pre_tmn = INFINITY;
-  // tile t of this workgroup's scan: (t0 + t) mod ntiles.  (The always-true tt < ntiles select
-  // in KNN_PREFETCH keeps `pre` in registers: without it the compiler places it in scratch.)
-#define KNN_TILE_AT(t) ((t0 + (t)) >= ntiles ? (t0 + (t)) - ntiles : (t0 + (t)))
+  float pre_thr = INFINITY;
+  float pre_tthr = INFINITY;
+  // tile of step t of this workgroup's scan: ws + ((s0 + t) mod L), taken mod ntp.  (The
+  // always-true tt < ntp select in KNN_PREFETCH keeps `pre` in registers: without it the
+  // compiler places it in scratch.)
+#define KNN_TILE_AT(t)                                                                        \
+  ([&](int64_t t_) {                                                                          \
+    int64_t u_ = s0 + t_;                                                                     \
+    if (u_ >= L) u_ -= L;                                                                     \
+    u_ += ws;                                                                                 \
+    return u_ >= ntp ? u_ - ntp : u_;                                                         \
+  })(t)
 #define KNN_PREFETCH(tt)                                                                      \
   {                                                                                           \
     const int64_t tt_ = (tt);                                                                 \
-    if (tid == 0) pre_tmn = tile_min[tt_];                                                    \
+    if (tid == 0) {                                                                           \
+      pre_tmn = tile_min[tt_];                                                                \
+      if (SYM) pre_tthr = args.tile_thr[tt_];                                                    \
+    }                                                                                         \
     const uint16_t* src_ = Xs + tt_ * (int64_t)(BT_C * DP);                                   \
-    _Pragma("unroll") for (int u = 0; u < CPT; u++) pre[u] = (tt_ < ntiles) ? *(const uint4*)(src_ + goff[u]) : make_uint4(0, 0, 0, 0); \
+    _Pragma("unroll") for (int u = 0; u < CPT; u++) pre[u] = (tt_ < ntp) ? *(const uint4*)(src_ + goff[u]) : make_uint4(0, 0, 0, 0); \
     if (tid < BT_C) {                                                                         \
       pre_inv = invs[tt_ * BT_C + tid];                                                       \
       pre_perm = perm[tt_ * BT_C + tid];                                                      \
+      if (SYM) pre_thr = args.colthr[tt_ * BT_C + tid];                                          \
     }                                                                                         \
   }
 #define KNN_COMMIT(b)                                                                         \
@@ -344,8 +447,12 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
     if (tid < BT_C) {                                                                         \
       tinv[b_ * BT_C + tid] = pre_inv;                                                        \
       tperm[b_ * BT_C + tid] = pre_perm;                                                      \
+      if (SYM) tthr[b_ * BT_C + tid] = pre_thr;                                               \
     }                                                                                         \
-    if (tid == 0) tmn[b_] = pre_tmn;                                                          \
+    if (tid == 0) {                                                                           \
+      tmn[b_] = pre_tmn;                                                                      \
+      if (SYM) tmn[2 + b_] = pre_tthr;                                                        \
+    }                                                                                         \
   }
 
   KNN_PREFETCH(KNN_TILE_AT(0));
@@ -382,6 +489,7 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
 
     // ---- epilogue: filter, then exact insertion for the rare hits
     const float mn = tmn[buf];
+    const int64_t tcur_tile = SYM ? KNN_TILE_AT(t) : 0;
 #pragma unroll
     for (int qb = 0; qb < NQB; qb++) {
       float m = -INFINITY;
@@ -436,6 +544,53 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
         }
         if (thr[qb] != INFINITY) thr[qb] = lwv[q];
       }
+      if (SYM) {
+        // candidate side: the lane's query i is a candidate of the 32 tile rows j it holds
+        // scores for, with raw score a / |x_i| in row j's units.  Since rounding is monotone,
+        // fl(m / |x_i|) below the tile's smallest threshold excludes all 32.
+        const float cq = colq[qb];
+        const bool ch = cq > 0.0f && m * cq >= tmn[2 + buf];
+        if (__ballot(ch)) {
+          uint32_t mask = 0;
+          if (ch) {
+#pragma unroll 1
+            for (int b = 0; b < 32; b++) {
+              const int i = b & 15;
+              const float sc = (b < 16 ? acc[0][qb][i] : acc[1][qb][i]) * cq;
+              if (sc >= tthr[buf * BT_C + (b >> 4) * 32 + 8 * (i / 4) + 4 * half + (i % 4)]) mask |= 1u << b;
+            }
+          }
+          // slots in the hand-over buffer: wave prefix sum of the counts, one atomic per wave
+          const int cnt = __popc(mask);
+          int incl = cnt;
+#pragma unroll
+          for (int o = 1; o < ANCKA_WAVE; o <<= 1) {
+            const int v = __shfl_up(incl, o, ANCKA_WAVE);
+            if (lane >= o) incl += v;
+          }
+          const int tot = __shfl(incl, ANCKA_WAVE - 1, ANCKA_WAVE);
+          unsigned long long base = 0;
+          if (lane == ANCKA_WAVE - 1 && tot > 0) base = atomicAdd(args.hcount, (unsigned long long)tot);
+          const unsigned lo = __shfl((unsigned)(base & 0xffffffffu), ANCKA_WAVE - 1, ANCKA_WAVE);
+          const unsigned hi = __shfl((unsigned)(base >> 32), ANCKA_WAVE - 1, ANCKA_WAVE);
+          uint64_t slot = (((uint64_t)hi << 32) | lo) + (uint64_t)(incl - cnt);
+          const uint64_t row0 = (uint64_t)tcur_tile * BT_C + 4 * half;
+          const uint64_t hv = (uint64_t)(uint32_t)qorig[qb] << 32;
+          // a wave-uniform loop over the 32 positions keeps this rare path compact
+#pragma unroll 1
+          for (int b = 0; b < 32; b++) {
+            if (mask & (1u << b)) {
+              const int i = b & 15;
+              const float sc = (b < 16 ? acc[0][qb][i] : acc[1][qb][i]) * cq;
+              if (slot < (uint64_t)args.hcap) {
+                args.hkey[slot] = row0 + (b >> 4) * 32 + 8 * (i / 4) + (i % 4);
+                args.hval[slot] = hv | __float_as_uint(sc);
+              }
+              slot++;
+            }
+          }
+        }
+      }
     }
 
     if (NBUF == 2) {
@@ -448,37 +603,103 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(
     }
   }
 
-  // sort each list (one thread per query), then write it with scores scaled by 1/|x_i| to cosines
+  // sort each list (one thread per query) and store it; the window pass also stores the
+  // candidate-side threshold of the row
   for (int q = tid; q < QB; q += 256) {
     const int64_t qs = q0 + q;
-    if (qs >= n) continue;
     float* ls = lsim + q * KPP;
     int* li = lidx + q * KPP;
-    for (int a = 1; a < KP; a++) {
-      const float sa = ls[a];
-      const int ja = li[a];
-      int b = a;
-      while (b > 0 && better<float>(sa, ja, ls[b - 1], li[b - 1])) {
+    for (int r = 1; r < KP; r++) {
+      const float sr = ls[r];
+      const int jr = li[r];
+      int b = r;
+      while (b > 0 && better<float>(sr, jr, ls[b - 1], li[b - 1])) {
         ls[b] = ls[b - 1];
         li[b] = li[b - 1];
         b--;
       }
-      ls[b] = sa;
-      li[b] = ja;
+      ls[b] = sr;
+      li[b] = jr;
     }
-    const int qi = perm[qs];
-    const float iq = invs[qs];
     for (int r = 0; r < KP; r++) {
-      const int j = li[r];
-      cand_idx[(int64_t)qi * KP + r] = (j == INT_MAX) ? -1 : j;
-      cand_sim[(int64_t)qi * KP + r] = (j == INT_MAX) ? 0.0f : ls[r] * iq;
+      args.lidx[qs * KP + r] = li[r];
+      args.lsim[qs * KP + r] = ls[r];
     }
+    if (!SYM) args.colthr[qs] = invs[qs] > 0.0f ? (li[KP - 1] != INT_MAX ? ls[KP - 1] : -INFINITY) : INFINITY;
   }
 }
 
 #undef KNN_TILE_AT
 #undef KNN_PREFETCH
 #undef KNN_COMMIT
+
+// smallest candidate-side threshold of each tile
+__global__ void tile_thr_kernel(const float* __restrict__ colthr, int64_t ntp, float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntp) return;
+  float m = INFINITY;
+  for (int r = 0; r < BT_C; r++) m = fminf(m, colthr[t * BT_C + r]);
+  out[t] = m;
+}
+
+// Final lists: row p's list (sorted best first) merged with the hand-over entries of row p
+// (hkey sorted, hn entries), then written at the original index with scores scaled by 1/|x_p|
+// to cosines.  One thread per row; the result is the top KP of the union under the (score,
+// index) order, whatever order the entries arrive in.
+__global__ __launch_bounds__(256) void knn_merge_kernel(int64_t n, int KP, const int32_t* __restrict__ lidx,
+                                                        const float* __restrict__ lsim, const float* __restrict__ invs,
+                                                        const int32_t* __restrict__ perm,
+                                                        const uint64_t* __restrict__ hkey,
+                                                        const uint64_t* __restrict__ hval, int64_t hn,
+                                                        int32_t* __restrict__ cand_idx, float* __restrict__ cand_sim) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int KPP = (KP + 3) & ~3;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= n) return;   // no barrier below: each thread works on its own slice of LDS
+  float* ls = (float*)smem + threadIdx.x * KPP;
+  int* li = (int*)((float*)smem + 256 * KPP) + threadIdx.x * KPP;
+  int wp = KP - 1;
+  for (int r = 0; r < KPP; r++) {
+    ls[r] = r < KP ? lsim[p * KP + r] : INFINITY;
+    li[r] = r < KP ? lidx[p * KP + r] : -1;
+    if (r < KP && li[r] == INT_MAX && wp == KP - 1 && r < KP - 1) wp = r;
+  }
+  if (hn > 0) {
+    float ws = ls[wp];
+    int wj = li[wp];
+    int64_t lo = 0, hi = hn;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (hkey[mid] < (uint64_t)p) lo = mid + 1;
+      else hi = mid;
+    }
+    for (int64_t e = lo; e < hn && hkey[e] == (uint64_t)p; e++) {
+      const uint64_t v = hval[e];
+      const float s = __uint_as_float((uint32_t)(v & 0xffffffffu));
+      const int j = (int)(v >> 32);
+      if (better<float>(s, j, ws, wj)) list_replace_worst(ls, li, KPP, s, j, ws, wj, wp);
+    }
+    for (int r = 1; r < KP; r++) {
+      const float sr = ls[r];
+      const int jr = li[r];
+      int b = r;
+      while (b > 0 && better<float>(sr, jr, ls[b - 1], li[b - 1])) {
+        ls[b] = ls[b - 1];
+        li[b] = li[b - 1];
+        b--;
+      }
+      ls[b] = sr;
+      li[b] = jr;
+    }
+  }
+  const int qi = perm[p];
+  const float iq = invs[p];
+  for (int r = 0; r < KP; r++) {
+    const int j = li[r];
+    cand_idx[(int64_t)qi * KP + r] = (j == INT_MAX) ? -1 : j;
+    cand_sim[(int64_t)qi * KP + r] = (j == INT_MAX) ? 0.0f : ls[r] * iq;
+  }
+}
 
 // cell of each row: the most similar of NPIV pivot rows (dot with the pivot scaled by its inverse
 // norm; ties to the smaller pivot).  Pivots are held in LDS as bf16; a thread owns a row and
@@ -537,6 +758,105 @@ __global__ __launch_bounds__(256) void cell_assign_kernel(const TX* __restrict__
   }
   keys[i] = ((uint64_t)best << 32) | (uint64_t)__float_as_uint(nrm[i]);
   vals[i] = (uint64_t)i;
+}
+
+// ---- pivots of the coarse cells: farthest-point sampling -------------------------------------
+// Over S evenly spaced rows (sample s is row s*n/S): the first pivot is the first non-zero sample;
+// each next one is the sample whose largest cosine with the pivots chosen so far is smallest
+// (ties to the smaller sample).  Zero rows are never chosen.  Well-separated groups of rows then
+// each receive a pivot before any group receives a second one, so a coarse cell rarely mixes
+// groups.  Iteration `it` folds pivot it into every sample's largest cosine (it = -1: start)
+// and leaves each block's arg-min; the select kernel takes the overall arg-min as pivot it+1.
+constexpr int FPS_S = 8192;
+
+__global__ __launch_bounds__(256) void fps_update_kernel(const uint16_t* __restrict__ X, int64_t n, int64_t d,
+                                                         int64_t ldx, int vec, const float* __restrict__ invn, int S,
+                                                         const int64_t* __restrict__ piv, int it,
+                                                         float* __restrict__ ms, float* __restrict__ bval,
+                                                         int* __restrict__ bidx) {
+  __shared__ float pv[512];
+  __shared__ float wv[4];
+  __shared__ int wi[4];
+  const int tid = threadIdx.x;
+  const int s = blockIdx.x * 256 + tid;
+  if (it >= 0) {
+    const int64_t pr = piv[it];
+    const float pi = invn[pr];
+    for (int c = tid; c < d; c += 256) pv[c] = bf16_to_f32(X[pr * ldx + c]) * pi;
+  }
+  __syncthreads();
+  float v = INFINITY;
+  int si = INT_MAX;
+  if (s < S) {
+    const int64_t r = (int64_t)s * n / S;
+    float m;
+    if (it < 0) {
+      m = invn[r] > 0.0f ? -INFINITY : INFINITY;
+    } else {
+      m = ms[s];
+      if (m != INFINITY) {
+        const uint16_t* xr = X + r * ldx;
+        float dot = 0.0f;
+        int64_t c = 0;
+        if (vec) {
+          for (; c + 8 <= d; c += 8) {
+            const uint4 w = *(const uint4*)(xr + c);
+            const uint32_t q[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+              dot = fmaf(__uint_as_float(q[u] << 16), pv[c + 2 * u], dot);
+              dot = fmaf(__uint_as_float(q[u] & 0xffff0000u), pv[c + 2 * u + 1], dot);
+            }
+          }
+        }
+        for (; c < d; c++) dot = fmaf(bf16_to_f32(xr[c]), pv[c], dot);
+        m = fmaxf(m, dot * invn[r]);
+      }
+      ms[s] = m;
+    }
+    if (it < 0) ms[s] = m;
+    v = m;
+    si = s;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const float ov = __shfl_xor(v, o, ANCKA_WAVE);
+    const int oi = __shfl_xor(si, o, ANCKA_WAVE);
+    if (ov < v || (ov == v && oi < si)) {
+      v = ov;
+      si = oi;
+    }
+  }
+  if (tid % ANCKA_WAVE == 0) {
+    wv[tid / ANCKA_WAVE] = v;
+    wi[tid / ANCKA_WAVE] = si;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 4; w++)
+      if (wv[w] < v || (wv[w] == v && wi[w] < si)) {
+        v = wv[w];
+        si = wi[w];
+      }
+    bval[blockIdx.x] = v;
+    bidx[blockIdx.x] = si;
+  }
+}
+
+// pivot it = the sample with the smallest value over the nb (<= 64) block candidates
+__global__ void fps_select_kernel(const float* __restrict__ bval, const int* __restrict__ bidx, int nb, int64_t n,
+                                  int S, int64_t* __restrict__ piv, int it) {
+  const int lane = threadIdx.x;
+  float v = lane < nb ? bval[lane] : INFINITY;
+  int si = lane < nb ? bidx[lane] : INT_MAX;
+  for (int o = 32; o > 0; o >>= 1) {
+    const float ov = __shfl_xor(v, o, ANCKA_WAVE);
+    const int oi = __shfl_xor(si, o, ANCKA_WAVE);
+    if (ov < v || (ov == v && oi < si)) {
+      v = ov;
+      si = oi;
+    }
+  }
+  if (lane == 0) piv[it] = si == INT_MAX ? 0 : (int64_t)si * n / S;
 }
 
 // Xs[p] = zero-padded bf16 row X[perm[p]], invs[p] = 1/|x_perm[p]|, perm[p]; rows n..npad-1
@@ -842,35 +1162,143 @@ constexpr int bf16_qb() {
 }
 int bf16_qw(int DP) { return DP <= 256 ? 64 : 32; }
 
-template <int DP, int QW, int NBUF>
-ancka_status run_bf16_t(ancka_ctx* ctx, const uint16_t* Xs, int64_t n, const float* invs, const int32_t* perm,
-                        const float* tmin, const int32_t* wg_start, int KP, int32_t* cidx, float* csim) {
+template <int DP, int QW, int NBUF, bool SYM>
+ancka_status run_bf16_t(ancka_ctx* ctx, const ScanArgs& args) {
   constexpr int QB = 4 * QW;
-  const int KPP = (KP + 3) & ~3;
-  const size_t sm = (size_t)NBUF * BT_C * (DP + 8) * 2 + 2 * NBUF * BT_C * 4 + 16 + (size_t)QB * KPP * 8 + (size_t)QB * 12;
+  const int KPP = (args.KP + 3) & ~3;
+  const size_t sm = (size_t)NBUF * BT_C * (DP + 8) * 2 + 2 * NBUF * BT_C * 4 + 16 + (size_t)QB * KPP * 8 +
+                    (size_t)QB * 12 + (SYM ? (size_t)NBUF * BT_C * 4 : 0);
   static bool attr_set = false;
   if (!attr_set) {
-    HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_bf16_kernel<DP, QW, NBUF>,
+    HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_bf16_kernel<DP, QW, NBUF, SYM>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     attr_set = true;
   }
-  if (sm > 160 * 1024) return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "knn: LDS budget exceeded (d=%d, K'=%d)", DP, KP);
-  knn_bf16_kernel<DP, QW, NBUF><<<(unsigned)cdiv(n, QB), 256, sm, ctx->stream>>>(Xs, n, invs, perm, tmin, wg_start, KP,
-                                                                                  cidx, csim);
+  if (sm > 160 * 1024) return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "knn: LDS budget exceeded (d=%d, K'=%d)", DP, args.KP);
+  knn_bf16_kernel<DP, QW, NBUF, SYM><<<(unsigned)args.nwg, 256, sm, ctx->stream>>>(args);
   LAUNCH_CHECK(ctx);
   return ANCKA_OK;
 }
 
-ancka_status run_bf16(ancka_ctx* ctx, int DP, const uint16_t* Xs, int64_t n, const float* invs, const int32_t* perm,
-                      const float* tmin, const int32_t* wg_start, int KP, int32_t* cidx, float* csim) {
+template <bool SYM>
+ancka_status run_bf16(ancka_ctx* ctx, int DP, const ScanArgs& args) {
   switch (DP) {
-    case 32: return run_bf16_t<32, 64, 2>(ctx, Xs, n, invs, perm, tmin, wg_start, KP, cidx, csim);
-    case 64: return run_bf16_t<64, 64, 2>(ctx, Xs, n, invs, perm, tmin, wg_start, KP, cidx, csim);
-    case 128: return run_bf16_t<128, 64, 2>(ctx, Xs, n, invs, perm, tmin, wg_start, KP, cidx, csim);
-    case 256: return run_bf16_t<256, 64, 2>(ctx, Xs, n, invs, perm, tmin, wg_start, KP, cidx, csim);
-    case 512: return run_bf16_t<512, 32, 1>(ctx, Xs, n, invs, perm, tmin, wg_start, KP, cidx, csim);
+    case 32: return run_bf16_t<32, 64, 2, SYM>(ctx, args);
+    case 64: return run_bf16_t<64, 64, 2, SYM>(ctx, args);
+    case 128: return run_bf16_t<128, 64, 2, SYM>(ctx, args);
+    case 256: return run_bf16_t<256, 64, 2, SYM>(ctx, args);
+    case 512: return run_bf16_t<512, 32, 1, SYM>(ctx, args);
     default: return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "knn: bf16 path supports d <= 512 (got padded %d)", DP);
   }
+}
+
+// Windows of the window pass, per block I as an unwrapped block range [lo, hi] with lo <= I <= hi.
+// Default: the blocks of the coarse cells that block I's rows belong to (cells are contiguous
+// row ranges cs[c] .. cs[c+1] of the scan order), so a row's window holds its whole cell.  With
+// ANCKA_KNN_WINDOW = w: blocks I-w .. I+w.  Both are symmetric (J in I's window iff I in J's).
+// Returns false (whole-ring scan instead) when a window would exceed a quarter of the ring, as
+// the symmetric pass assumes.
+bool scan_windows(int64_t n, int64_t nwg, int QB, const int64_t* hcs, std::vector<int32_t>& lo,
+                  std::vector<int32_t>& hi) {
+  lo.assign(nwg, 0);
+  hi.assign(nwg, 0);
+  const int64_t cap = nwg / 4;
+  if (const char* e = getenv("ANCKA_KNN_WINDOW")) {
+    int64_t w = atoll(e);
+    if (w < 0) w = 0;
+    if (2 * w + 1 > cap) return false;
+    for (int64_t I = 0; I < nwg; I++) {
+      lo[I] = (int32_t)(I - w);
+      hi[I] = (int32_t)(I + w);
+    }
+    return true;
+  }
+  auto cell_of = [&](int64_t p) {   // last cell c with hcs[c] <= p (empty cells skipped)
+    int c = 0;
+    while (c + 1 < NPIV && hcs[c + 1] <= p) c++;
+    return c;
+  };
+  for (int64_t I = 0; I < nwg; I++) {
+    const int64_t p0 = I * QB, p1 = std::min(n, (I + 1) * QB) - 1;
+    const int c0 = cell_of(p0), c1 = cell_of(p1);
+    lo[I] = (int32_t)(hcs[c0] / QB);
+    hi[I] = (I == nwg - 1) ? (int32_t)(nwg - 1) : (int32_t)((hcs[c1 + 1] - 1) / QB);
+    if (hi[I] - lo[I] + 1 > cap) return false;
+  }
+  return true;
+}
+
+// Capacity (entries) of the hand-over buffer: ANCKA_KNN_HANDOVER or max(16 n, 2^22).
+int64_t handover_capacity(int64_t n) {
+  int64_t c = 16 * n > ((int64_t)1 << 22) ? 16 * n : ((int64_t)1 << 22);
+  if (const char* e = getenv("ANCKA_KNN_HANDOVER")) c = atoll(e);
+  return c < 1 ? 1 : c;
+}
+
+// BF16 tile phase: window pass, symmetric pass, sort of the hand-over entries by row, merge.
+// If the hand-over buffer overflows the window pass is redone over the whole ring instead.
+ancka_status bf16_scan(ancka_ctx* ctx, int DP, ScanArgs args, const std::vector<int32_t>& hlo,
+                       const std::vector<int32_t>& hhi, int64_t n, int32_t* cidx, float* csim, ancka_knn_stats* st) {
+  hipEvent_t* ev = nullptr;
+  ST_TRY(ctx_events(ctx, &ev));
+  int64_t hn = 0;
+  bool timed_sym = false;
+  ST_TRY(run_bf16<false>(ctx, DP, args));
+  if (args.w >= 0) {
+    tile_thr_kernel<<<(unsigned)cdiv(args.ntp, 256), 256, 0, ctx->stream>>>(args.colthr, args.ntp,
+                                                                             (float*)args.tile_thr);
+    LAUNCH_CHECK(ctx);
+    ST_TRY(fill_zero(ctx, args.hcount, sizeof(unsigned long long)));
+    HIP_TRY(ctx, hipEventRecord(ev[4], ctx->stream));
+    ST_TRY(run_bf16<true>(ctx, DP, args));
+    HIP_TRY(ctx, hipEventRecord(ev[5], ctx->stream));
+    timed_sym = true;
+    unsigned long long hc = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&hc, args.hcount, sizeof(hc), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (st) st->handed_over = (int64_t)hc;
+    if ((int64_t)hc > args.hcap) {
+      args.w = -1;
+      ST_TRY(run_bf16<false>(ctx, DP, args));
+      if (st) st->rescanned = 1;
+    } else {
+      hn = (int64_t)hc;
+      int bits = 1;
+      while (bits < 63 && ((int64_t)1 << bits) < args.nwg * 4 * bf16_qw(DP)) bits++;
+      ST_TRY(radix_sort_u64(ctx, args.hkey, args.hval, hn, bits));
+    }
+  }
+  const int KPP = (args.KP + 3) & ~3;
+  static bool mattr = false;
+  if (!mattr) {
+    HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_merge_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     160 * 1024));
+    mattr = true;
+  }
+  knn_merge_kernel<<<(unsigned)cdiv(n, 256), 256, (size_t)256 * KPP * 8, ctx->stream>>>(
+      n, args.KP, args.lidx, args.lsim, args.invs, args.perm, args.hkey, args.hval, hn, cidx, csim);
+  LAUNCH_CHECK(ctx);
+  if (st) {
+    int32_t wmax = -1;
+    if (args.w >= 0)
+      for (size_t I = 0; I < hlo.size(); I++) wmax = std::max(wmax, hhi[I] - hlo[I] + 1);
+    st->window = wmax;
+    if (timed_sym) {
+      HIP_TRY(ctx, hipEventSynchronize(ev[5]));
+      float ms = 0.f;
+      HIP_TRY(ctx, hipEventElapsedTime(&ms, ev[4], ev[5]));
+      st->sym_ms = ms;
+      // unordered pairs of rows the symmetric pass scores (padding rows included)
+      const int64_t QB = 4 * bf16_qw(DP), nwg = args.nwg;
+      int64_t blocks = 0;
+      for (int64_t I = 0; I < nwg; I++) {
+        const int64_t hb = (nwg % 2 == 0 && I >= nwg / 2) ? nwg / 2 - 1 : nwg / 2;
+        if (I + hb > hhi[I]) blocks += I + hb - hhi[I];
+      }
+      st->sym_pairs = blocks * QB * QB;
+    }
+  }
+  return ANCKA_OK;
 }
 
 template <typename TX>
@@ -944,9 +1372,9 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
     } else {
       // scan order: rows grouped by coarse cell (nearest of NPIV pivot rows), by norm inside a
       // cell; a zero-padded bf16 copy Xs in that order serves as queries and candidates
-      const int64_t nt = cdiv(n, BT_C);
       const int QB = 4 * bf16_qw(DP);
       const int64_t nwg = cdiv(n, QB);
+      const int64_t nt = nwg * (QB / BT_C);   // tiles of the padded ring
       float *tmin = nullptr, *invs = nullptr;
       uint64_t *keys = nullptr, *order = nullptr;
       int64_t* piv = nullptr;
@@ -962,11 +1390,25 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
       ST_TRY(ws_get_t(ctx, "knn_perm", (size_t)npad, &perm));
       ST_TRY(ws_get_t(ctx, "knn_wgs", (size_t)nwg, &wgs));
       ST_TRY(ws_get_t(ctx, "knn_xs", (size_t)npad * DP, &Xs));
-      // pivots: evenly spaced rows (a zero pivot row only yields an unused cell)
-      int64_t hp[NPIV];
-      for (int p = 0; p < NPIV; p++) hp[p] = (int64_t)((double)p * (double)n / NPIV);
-      HIP_TRY(ctx, hipMemcpyAsync(piv, hp, sizeof(hp), hipMemcpyHostToDevice, ctx->stream));
-      HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));   // hp is a stack array
+      // pivots: farthest-point sampling over FPS_S evenly spaced rows
+      {
+        const int S = (int)std::min<int64_t>(n, FPS_S);
+        const int nb = (int)cdiv(S, 256);
+        float *fms = nullptr, *fbv = nullptr;
+        int* fbi = nullptr;
+        ST_TRY(ws_get_t(ctx, "knn_fps_ms", (size_t)S, &fms));
+        ST_TRY(ws_get_t(ctx, "knn_fps_bv", (size_t)nb, &fbv));
+        ST_TRY(ws_get_t(ctx, "knn_fps_bi", (size_t)nb, &fbi));
+        const int vec = (ldx % 8 == 0 && ((uintptr_t)X % 16) == 0) ? 1 : 0;
+        const uint16_t* Xb = (const uint16_t*)(const void*)X;
+        for (int it = -1; it < NPIV - 1; it++) {
+          fps_update_kernel<<<(unsigned)nb, 256, 0, ctx->stream>>>(Xb, n, d, ldx, vec, invn, S, piv, it, fms, fbv,
+                                                                   fbi);
+          LAUNCH_CHECK(ctx);
+          fps_select_kernel<<<1, ANCKA_WAVE, 0, ctx->stream>>>(fbv, fbi, nb, n, S, piv, it + 1);
+          LAUNCH_CHECK(ctx);
+        }
+      }
       const size_t csm = (size_t)NPIV * ((d + 7) / 8 * 8) * 2 + NPIV * 4;
       static bool cattr = false;
       if (!cattr) {
@@ -1007,8 +1449,38 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
       LAUNCH_CHECK(ctx);
       wg_start_kernel<<<(unsigned)cdiv(nwg, 256), 256, 0, ctx->stream>>>(keys, n, QB, nwg, 0, wgs);
       LAUNCH_CHECK(ctx);
+      ScanArgs sa{};
+      sa.Xs = Xs;
+      sa.invs = invs;
+      sa.perm = perm;
+      sa.tile_min = tmin;
+      sa.wg_start = wgs;
+      sa.nwg = nwg;
+      sa.ntp = nt;
+      std::vector<int32_t> hlo, hhi;
+      sa.w = scan_windows(n, nwg, QB, hcs, hlo, hhi) ? 0 : -1;
+      sa.KP = KP;
+      ST_TRY(ws_get_t(ctx, "knn_lidx", (size_t)npad * KP, &sa.lidx));
+      ST_TRY(ws_get_t(ctx, "knn_lsim", (size_t)npad * KP, &sa.lsim));
+      ST_TRY(ws_get_t(ctx, "knn_colthr", (size_t)npad, &sa.colthr));
+      if (sa.w >= 0) {
+        int32_t *wlo = nullptr, *whi = nullptr;
+        ST_TRY(ws_get_t(ctx, "knn_wlo", (size_t)nwg, &wlo));
+        ST_TRY(ws_get_t(ctx, "knn_whi", (size_t)nwg, &whi));
+        HIP_TRY(ctx, hipMemcpyAsync(wlo, hlo.data(), nwg * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(whi, hhi.data(), nwg * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+        sa.wlo = wlo;
+        sa.whi = whi;
+        float* tthr = nullptr;
+        ST_TRY(ws_get_t(ctx, "knn_tthr", (size_t)nt, &tthr));
+        sa.tile_thr = tthr;
+        sa.hcap = handover_capacity(n);
+        ST_TRY(ws_get_t(ctx, "knn_hkey", (size_t)sa.hcap, &sa.hkey));
+        ST_TRY(ws_get_t(ctx, "knn_hval", (size_t)sa.hcap, &sa.hval));
+        ST_TRY(ws_get_t(ctx, "knn_hcount", 1, &sa.hcount));
+      }
       HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
-      ST_TRY(run_bf16(ctx, DP, Xs, n, invs, perm, tmin, wgs, KP, cidx, csim));
+      ST_TRY(bf16_scan(ctx, DP, sa, hlo, hhi, n, cidx, csim, st));
       HIP_TRY(ctx, hipEventRecord(ev[2], ctx->stream));
     }
     ST_TRY(rescore_and_fix<TX>(ctx, X, n, d, ldx, sq, KP, K, cidx, csim, nbr_idx, (float*)nbr_sim, st));
@@ -1077,7 +1549,7 @@ extern "C" ancka_status ancka_knn(ancka_ctx* ctx, const void* X, int32_t xdtype,
   if (mode == ANCKA_KNN_BF16_RESCORE && xdtype != ANCKA_BF16)
     return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "ancka_knn: BF16_RESCORE needs bf16 attributes");
   if (mode < 0 || mode > 2) return set_err(ctx, ANCKA_ERR_INVALID_ARG, "ancka_knn: unknown mode %d", mode);
-  if (stats) *stats = ancka_knn_stats{0, 0, 0, 0.0, 0.0};
+  if (stats) *stats = ancka_knn_stats{0, 0, 0, 0.0, 0.0, 0.0, 0, 0, -1, 0};
   switch (xdtype) {
     case ANCKA_F64: return knn_typed<double>(ctx, (const double*)X, n, d, ldx, K, mode, nbr_idx, nbr_sim, stats);
     case ANCKA_F32: return knn_typed<float>(ctx, (const float*)X, n, d, ldx, K, mode, nbr_idx, nbr_sim, stats);

@@ -23,6 +23,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t v) { return __uint_as_float(((uint32_t)v) << 16); }
 
@@ -217,6 +218,8 @@ __global__ __launch_bounds__(256) void knn_vector_kernel(const TX* __restrict__ 
 // query's sorted list in LDS; the two half-waves, which hold different candidates of the same
 // queries, insert one after the other.
 constexpr int BT_C = 64;   // candidates per tile
+constexpr int TAU_T = 11;  // bound pass: values kept per lane (lists up to 2 TAU_T - 1 = 21 long)
+enum { SCAN_WIN = 0, SCAN_SYM = 1, SCAN_TAU = 2 };
 constexpr int NPIV = 64;   // coarse cells of the scan order
 
 // One query's candidate list in LDS, unsorted: kpp slots (the list length rounded up to 4;
@@ -274,14 +277,19 @@ struct ScanArgs {
   float* colthr;             // [npad] candidate-side threshold: the list's worst raw score after
                              // the window pass (-inf if not full; +inf for zero and padding rows)
   const float* tile_thr;     // [ntp] smallest colthr of each tile (symmetric pass)
+  const float* tile_cinv;    // [ntp] smallest 1/|x| of a non-zero row of each tile (bound pass)
+  float* tau;                // [npad] lower bound of each row's KP-th best raw score (bound pass
+                             //   writes it, window pass starts from it); nullptr: none
   uint64_t* hkey;            // hand-over buffer: sorted row that receives the candidate
   uint64_t* hval;            //   (original index of the candidate << 32) | raw score bits
   unsigned long long* hcount;  // entries produced (may exceed hcap: then the buffer overflowed)
   int64_t hcap;
 };
 
-template <int DP, int QW, int NBUF, bool SYM>
+template <int DP, int QW, int NBUF, int MODE>
 __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(ScanArgs args) {
+  constexpr bool SYM = MODE == SCAN_SYM;
+  constexpr bool TAU = MODE == SCAN_TAU;
   constexpr int KS = DP / 16;           // MFMA k-steps
   constexpr int NQB = QW / 32;          // query blocks per wave
   constexpr int QB = 4 * QW;            // queries per workgroup
@@ -314,7 +322,7 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
   const int64_t blk = blockIdx.x;
   const int64_t q0 = blk * QB;
 
-  if (!SYM) {
+  if (MODE == SCAN_WIN) {
     for (int e = tid; e < QB * KPP; e += 256) {
       const bool pad = (e % KPP) >= KP;
       lsim[e] = pad ? INFINITY : -INFINITY;
@@ -325,7 +333,7 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
       lwi[q] = INT_MAX;
       lwp[q] = 0;
     }
-  } else {
+  } else if (SYM) {
     // the window pass's lists (sorted best first): the worst entry is the first empty slot, or
     // the last slot of a full list
     for (int e = tid; e < QB * KPP; e += 256) {
@@ -348,7 +356,9 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
   // query fragments: lane holds 8 bf16 of query row (l32) at k = ks*16 + half*8
   bf16x8 bq[NQB][KS];
   float thr[NQB];
+  float tq[NQB];     // window pass: the bound pass's lower bound, a floor for the threshold
   float colq[NQB];   // symmetric pass: 1/|x_i| of the lane's query (0: the query takes no part)
+  float rt[NQB][TAU_T];  // bound pass: the lane's TAU_T largest bound scores, descending
   int qloc[NQB];
   int qorig[NQB];
   // Xs, invs and perm are padded with zero rows (invs 0, perm -1) to whole workgroups, so no
@@ -360,8 +370,11 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
     const int64_t qs = q0 + qloc[qb];
     qorig[qb] = args.perm[qs];
     const float iq = args.invs[qs];
-    thr[qb] = iq > 0.0f ? (SYM ? lwv[qloc[qb]] : -INFINITY) : INFINITY;
+    tq[qb] = (MODE == SCAN_WIN && args.tau) ? args.tau[qs] : -INFINITY;
+    thr[qb] = iq > 0.0f ? (SYM ? lwv[qloc[qb]] : tq[qb]) : INFINITY;
     colq[qb] = iq;
+#pragma unroll
+    for (int j = 0; j < TAU_T; j++) rt[qb][j] = -INFINITY;
 #pragma unroll
     for (int ks = 0; ks < KS; ks++) {
       const uint4 v = *(const uint4*)(args.Xs + qs * DP + ks * 16 + half * 8);
@@ -408,15 +421,15 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
     goff[u] = r * DP + c8 * 8;
     loff[u] = r * LDR + c8 * 8;
   }
-  uint4 pre[CPT];
+  u32x4 pre[CPT];   // a native vector type: the HIP uint4 struct keeps this array out of registers
   float pre_inv = 0.0f;
   int pre_perm = -1;
   float pre_tmn = INFINITY;
   float pre_thr = INFINITY;
   float pre_tthr = INFINITY;
-  // tile of step t of this workgroup's scan: ws + ((s0 + t) mod L), taken mod ntp.  (The
-  // always-true tt < ntp select in KNN_PREFETCH keeps `pre` in registers: without it the
-  // compiler places it in scratch.)
+  // tile of step t of this workgroup's scan: ws + ((s0 + t) mod L), taken mod ntp.  Every step
+  // prefetches and commits a tile (the last step re-loads its own tile into the idle buffer):
+  // with no conditional load the compiler needs no wait for stale loads at the loop head.
 #define KNN_TILE_AT(t)                                                                        \
   ([&](int64_t t_) {                                                                          \
     int64_t u_ = s0 + t_;                                                                     \
@@ -427,23 +440,21 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
 #define KNN_PREFETCH(tt)                                                                      \
   {                                                                                           \
     const int64_t tt_ = (tt);                                                                 \
-    if (tid == 0) {                                                                           \
-      pre_tmn = tile_min[tt_];                                                                \
-      if (SYM) pre_tthr = args.tile_thr[tt_];                                                    \
-    }                                                                                         \
+    pre_tmn = tile_min[tt_];                                                                  \
+    if (SYM) pre_tthr = args.tile_thr[tt_];                                                   \
+    if (TAU) pre_tthr = args.tile_cinv[tt_];                                                  \
     const uint16_t* src_ = Xs + tt_ * (int64_t)(BT_C * DP);                                   \
-    _Pragma("unroll") for (int u = 0; u < CPT; u++) pre[u] = (tt_ < ntp) ? *(const uint4*)(src_ + goff[u]) : make_uint4(0, 0, 0, 0); \
-    if (tid < BT_C) {                                                                         \
-      pre_inv = invs[tt_ * BT_C + tid];                                                       \
-      pre_perm = perm[tt_ * BT_C + tid];                                                      \
-      if (SYM) pre_thr = args.colthr[tt_ * BT_C + tid];                                          \
-    }                                                                                         \
+    _Pragma("unroll") for (int u = 0; u < CPT; u++) pre[u] = *(const u32x4*)(src_ + goff[u]); \
+    const int64_t r_ = tt_ * BT_C + (tid & (BT_C - 1));                                       \
+    pre_inv = invs[r_];                                                                       \
+    pre_perm = perm[r_];                                                                      \
+    if (SYM) pre_thr = args.colthr[r_];                                                       \
   }
 #define KNN_COMMIT(b)                                                                         \
   {                                                                                           \
     const int b_ = (b);                                                                       \
     uint16_t* dst_ = tileb + b_ * BT_C * LDR;                                                 \
-    _Pragma("unroll") for (int u = 0; u < CPT; u++) *(uint4*)(dst_ + loff[u]) = pre[u];       \
+    _Pragma("unroll") for (int u = 0; u < CPT; u++) *(u32x4*)(dst_ + loff[u]) = pre[u];       \
     if (tid < BT_C) {                                                                         \
       tinv[b_ * BT_C + tid] = pre_inv;                                                        \
       tperm[b_ * BT_C + tid] = pre_perm;                                                      \
@@ -451,7 +462,7 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
     }                                                                                         \
     if (tid == 0) {                                                                           \
       tmn[b_] = pre_tmn;                                                                      \
-      if (SYM) tmn[2 + b_] = pre_tthr;                                                        \
+      if (SYM || TAU) tmn[2 + b_] = pre_tthr;                                                 \
     }                                                                                         \
   }
 
@@ -461,7 +472,7 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
 
   for (int64_t t = 0; t < ntiles; t++) {
     const int buf = NBUF == 2 ? (int)(t & 1) : 0;
-    if (t + 1 < ntiles) KNN_PREFETCH(KNN_TILE_AT(t + 1));
+    KNN_PREFETCH(KNN_TILE_AT(t + 1 < ntiles ? t + 1 : t));
 
     f32x16 acc[2][NQB];
 #pragma unroll
@@ -497,6 +508,29 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
       for (int cb = 0; cb < 2; cb++)
 #pragma unroll
         for (int i = 0; i < 16; i++) m = fmaxf(m, acc[cb][qb][i]);
+      if (TAU) {
+        // bound scores a * c, c the tile's smallest 1/|x_j|: for a > 0 no larger than the
+        // list score a / |x_j| (rounding is monotone); the lane keeps its TAU_T largest
+        const float c = tmn[2 + buf];
+        if (__ballot(m * c > rt[qb][TAU_T - 1])) {
+#pragma unroll
+          for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int i = 0; i < 16; i++) {
+              const float av = acc[cb][qb][i];
+              float x = av * c;
+              if (av > 0.0f && x > rt[qb][TAU_T - 1]) {
+#pragma unroll
+                for (int j = 0; j < TAU_T; j++) {
+                  const float hi = fmaxf(rt[qb][j], x);
+                  x = fminf(rt[qb][j], x);
+                  rt[qb][j] = hi;
+                }
+              }
+            }
+        }
+        continue;
+      }
       const float th = thr[qb];
       const float fth = (th >= 0.0f) ? th * mn * (1.0f - 1e-6f) : (th == INFINITY ? INFINITY : -INFINITY);
       const bool hit = m >= fth;
@@ -542,7 +576,7 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
           // memory fence here would also wait for the next tile's global loads in flight.
           asm volatile("" ::: "memory");
         }
-        if (thr[qb] != INFINITY) thr[qb] = lwv[q];
+        if (thr[qb] != INFINITY) thr[qb] = fmaxf(lwv[q], tq[qb]);
       }
       if (SYM) {
         // candidate side: the lane's query i is a candidate of the 32 tile rows j it holds
@@ -594,15 +628,30 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
     }
 
     if (NBUF == 2) {
-      if (t + 1 < ntiles) KNN_COMMIT(buf ^ 1);
+      KNN_COMMIT(buf ^ 1);
       __syncthreads();
     } else {
       __syncthreads();            // every wave is done with the single buffer
-      if (t + 1 < ntiles) KNN_COMMIT(0);
+      KNN_COMMIT(0);
       __syncthreads();
     }
   }
 
+  if (TAU) {
+    // The two halves of a lane pair hold disjoint candidates of one query, so their 2 TAU_T
+    // values belong to 2 TAU_T distinct candidates (at most one of them the query itself), each
+    // with a list score at least the smaller of the two TAU_T-th values.  With 2 TAU_T - 1 >= KP
+    // that value is a lower bound of the query's KP-th best list score; -inf when a half saw
+    // fewer than TAU_T positive scores, or when KP is too long for TAU_T.
+#pragma unroll
+    for (int qb = 0; qb < NQB; qb++) {
+      const float own = rt[qb][TAU_T - 1];
+      const float other = __shfl_xor(own, 32, ANCKA_WAVE);
+      const float t = fminf(own, other);
+      if (half == 0) args.tau[q0 + qloc[qb]] = (2 * TAU_T - 1 >= KP && t > 0.0f) ? t : -INFINITY;
+    }
+    return;
+  }
   // sort each list (one thread per query) and store it; the window pass also stores the
   // candidate-side threshold of the row
   for (int q = tid; q < QB; q += 256) {
@@ -888,18 +937,23 @@ __global__ __launch_bounds__(256) void gather_sorted_kernel(const uint16_t* __re
   }
 }
 
-// per tile of ordered candidates: the smallest norm of a non-zero row (+inf if none)
+// per tile of ordered candidates: the smallest norm of a non-zero row (+inf if none) and the
+// smallest inverse norm of a non-zero row (0 if none)
 __global__ void tile_min_sorted_kernel(const float* __restrict__ invs, int64_t n, int tile, float* __restrict__ out,
-                                       int64_t ntiles) {
+                                       float* __restrict__ cinv, int64_t ntiles) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ntiles) return;
-  float m = INFINITY;
+  float m = INFINITY, c = INFINITY;
   for (int64_t j = t * tile; j < n && j < (t + 1) * tile; j++) {
     const float iv = invs[j];
-    if (iv > 0.0f) m = fminf(m, 1.0f / iv);
+    if (iv > 0.0f) {
+      m = fminf(m, 1.0f / iv);
+      c = fminf(c, iv);
+    }
   }
   // 1/iv rounds; shrink by a few ulps so the bound stays below every |x_j| as seen through 1/|x_j|
   out[t] = m * (1.0f - 4e-7f);
+  cinv[t] = c == INFINITY ? 0.0f : c;
 }
 
 // cs[c] = first sorted position of cell c (keys sorted by cell << 32 | norm), cs[NPIV] = n
@@ -1162,32 +1216,34 @@ constexpr int bf16_qb() {
 }
 int bf16_qw(int DP) { return DP <= 256 ? 64 : 32; }
 
-template <int DP, int QW, int NBUF, bool SYM>
+template <int DP, int QW, int NBUF, int MODE>
 ancka_status run_bf16_t(ancka_ctx* ctx, const ScanArgs& args) {
+  constexpr bool SYM = MODE == SCAN_SYM;
   constexpr int QB = 4 * QW;
   const int KPP = (args.KP + 3) & ~3;
-  const size_t sm = (size_t)NBUF * BT_C * (DP + 8) * 2 + 2 * NBUF * BT_C * 4 + 16 + (size_t)QB * KPP * 8 +
-                    (size_t)QB * 12 + (SYM ? (size_t)NBUF * BT_C * 4 : 0);
+  const size_t sm = (size_t)NBUF * BT_C * (DP + 8) * 2 + 2 * NBUF * BT_C * 4 + 16 +
+                    (MODE == SCAN_TAU ? 0 : (size_t)QB * KPP * 8 + (size_t)QB * 12) +
+                    (SYM ? (size_t)NBUF * BT_C * 4 : 0);
   static bool attr_set = false;
   if (!attr_set) {
-    HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_bf16_kernel<DP, QW, NBUF, SYM>,
+    HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_bf16_kernel<DP, QW, NBUF, MODE>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     attr_set = true;
   }
   if (sm > 160 * 1024) return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "knn: LDS budget exceeded (d=%d, K'=%d)", DP, args.KP);
-  knn_bf16_kernel<DP, QW, NBUF, SYM><<<(unsigned)args.nwg, 256, sm, ctx->stream>>>(args);
+  knn_bf16_kernel<DP, QW, NBUF, MODE><<<(unsigned)args.nwg, 256, sm, ctx->stream>>>(args);
   LAUNCH_CHECK(ctx);
   return ANCKA_OK;
 }
 
-template <bool SYM>
+template <int MODE>
 ancka_status run_bf16(ancka_ctx* ctx, int DP, const ScanArgs& args) {
   switch (DP) {
-    case 32: return run_bf16_t<32, 64, 2, SYM>(ctx, args);
-    case 64: return run_bf16_t<64, 64, 2, SYM>(ctx, args);
-    case 128: return run_bf16_t<128, 64, 2, SYM>(ctx, args);
-    case 256: return run_bf16_t<256, 64, 2, SYM>(ctx, args);
-    case 512: return run_bf16_t<512, 32, 1, SYM>(ctx, args);
+    case 32: return run_bf16_t<32, 64, 2, MODE>(ctx, args);
+    case 64: return run_bf16_t<64, 64, 2, MODE>(ctx, args);
+    case 128: return run_bf16_t<128, 64, 2, MODE>(ctx, args);
+    case 256: return run_bf16_t<256, 64, 2, MODE>(ctx, args);
+    case 512: return run_bf16_t<512, 32, 1, MODE>(ctx, args);
     default: return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "knn: bf16 path supports d <= 512 (got padded %d)", DP);
   }
 }
@@ -1243,14 +1299,15 @@ ancka_status bf16_scan(ancka_ctx* ctx, int DP, ScanArgs args, const std::vector<
   ST_TRY(ctx_events(ctx, &ev));
   int64_t hn = 0;
   bool timed_sym = false;
-  ST_TRY(run_bf16<false>(ctx, DP, args));
+  if (args.w >= 0 && args.tau) ST_TRY(run_bf16<SCAN_TAU>(ctx, DP, args));
+  ST_TRY(run_bf16<SCAN_WIN>(ctx, DP, args));
   if (args.w >= 0) {
     tile_thr_kernel<<<(unsigned)cdiv(args.ntp, 256), 256, 0, ctx->stream>>>(args.colthr, args.ntp,
                                                                              (float*)args.tile_thr);
     LAUNCH_CHECK(ctx);
     ST_TRY(fill_zero(ctx, args.hcount, sizeof(unsigned long long)));
     HIP_TRY(ctx, hipEventRecord(ev[4], ctx->stream));
-    ST_TRY(run_bf16<true>(ctx, DP, args));
+    ST_TRY(run_bf16<SCAN_SYM>(ctx, DP, args));
     HIP_TRY(ctx, hipEventRecord(ev[5], ctx->stream));
     timed_sym = true;
     unsigned long long hc = 0;
@@ -1259,7 +1316,7 @@ ancka_status bf16_scan(ancka_ctx* ctx, int DP, ScanArgs args, const std::vector<
     if (st) st->handed_over = (int64_t)hc;
     if ((int64_t)hc > args.hcap) {
       args.w = -1;
-      ST_TRY(run_bf16<false>(ctx, DP, args));
+      ST_TRY(run_bf16<SCAN_WIN>(ctx, DP, args));
       if (st) st->rescanned = 1;
     } else {
       hn = (int64_t)hc;
@@ -1445,7 +1502,9 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
       gather_sorted_kernel<<<(unsigned)cdiv(npad, 4), 256, 0, ctx->stream>>>((const uint16_t*)(const void*)X, n, npad,
                                                                              d, ldx, order, invn, DP, Xs, invs, perm);
       LAUNCH_CHECK(ctx);
-      tile_min_sorted_kernel<<<(unsigned)cdiv(nt, 256), 256, 0, ctx->stream>>>(invs, n, BT_C, tmin, nt);
+      float* tcinv = nullptr;
+      ST_TRY(ws_get_t(ctx, "knn_tcinv", (size_t)nt, &tcinv));
+      tile_min_sorted_kernel<<<(unsigned)cdiv(nt, 256), 256, 0, ctx->stream>>>(invs, n, BT_C, tmin, tcinv, nt);
       LAUNCH_CHECK(ctx);
       wg_start_kernel<<<(unsigned)cdiv(nwg, 256), 256, 0, ctx->stream>>>(keys, n, QB, nwg, 0, wgs);
       LAUNCH_CHECK(ctx);
@@ -1474,6 +1533,8 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
         float* tthr = nullptr;
         ST_TRY(ws_get_t(ctx, "knn_tthr", (size_t)nt, &tthr));
         sa.tile_thr = tthr;
+        sa.tile_cinv = tcinv;
+        if (2 * TAU_T - 1 >= KP) ST_TRY(ws_get_t(ctx, "knn_tau", (size_t)npad, &sa.tau));
         sa.hcap = handover_capacity(n);
         ST_TRY(ws_get_t(ctx, "knn_hkey", (size_t)sa.hcap, &sa.hkey));
         ST_TRY(ws_get_t(ctx, "knn_hval", (size_t)sa.hcap, &sa.hval));

@@ -95,3 +95,16 @@ def test_default_window_uses_symmetric_pass(lib, monkeypatch):
     assert 0 < st.sym_pairs <= sym_pairs(nwg, 0)
     rows = np.sort(np.random.default_rng(1).choice(n, 200, replace=False))
     assert check_knn_rows(X.astype(np.float32), rows, gi[rows], gs[rows], 10, 2 * gamma_d(128, 2.0 ** -24)) <= 1
+
+
+@pytest.mark.parametrize("K", [10, 11, 16])
+def test_list_lengths_around_the_bound_pass(lib, monkeypatch, K):
+    # 2K <= 21: the window pass starts from the bound pass's lower bounds; longer lists skip it
+    n = 9000
+    X = data(n, 21 + K)
+    gi_w, gs_w, st_w = run(lib, X, K, monkeypatch, window=2)
+    gi_f, gs_f, st_f = run(lib, X, K, monkeypatch, window=n)
+    assert st_w.window == 5 and st_f.window == -1
+    assert np.array_equal(gi_w, gi_f) and np.array_equal(gs_w, gs_f)
+    rows = np.sort(np.random.default_rng(K).choice(n, 150, replace=False))
+    assert check_knn_rows(X.astype(np.float32), rows, gi_f[rows], gs_f[rows], K, 2 * gamma_d(128, 2.0 ** -24)) <= 1

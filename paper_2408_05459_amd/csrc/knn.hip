@@ -14,6 +14,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 #include <vector>
 #include <algorithm>
 
@@ -383,16 +384,18 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
   }
 
   // this workgroup's scan: L tiles of the ring starting at tile ws, beginning at offset s0
-  const int64_t ntp = args.ntp;
-  int64_t ws, L, s0;
+  // tile indices fit in 32 bits (ntp < 2^26 for n < 2^31 rows); fewer 64-bit scalars keeps the
+  // loop's scalar registers from spilling
+  const int ntp = (int)args.ntp;
+  int ws, L, s0;
   if (!SYM) {
     if (args.w < 0) {
       ws = 0;
       L = ntp;
       s0 = args.wg_start[blk];
     } else {
-      const int64_t lo = args.wlo[blk], hi = args.whi[blk];
-      int64_t b0 = lo;
+      const int lo = args.wlo[blk], hi = args.whi[blk];
+      int b0 = lo;
       if (b0 < 0) b0 += args.nwg;
       ws = b0 * TPB;
       L = (hi - lo + 1) * TPB;
@@ -401,13 +404,14 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
       if (s0 >= L) s0 = (blk - lo) * TPB;
     }
   } else {
-    const int64_t hb = (args.nwg % 2 == 0 && blk >= args.nwg / 2) ? args.nwg / 2 - 1 : args.nwg / 2;
-    const int64_t hi = args.whi[blk];
+    const int nwg = (int)args.nwg, bk = (int)blk;
+    const int hb = (nwg % 2 == 0 && bk >= nwg / 2) ? nwg / 2 - 1 : nwg / 2;
+    const int hi = args.whi[blk];
     ws = ((hi + 1) % args.nwg) * TPB;
     L = blk + hb > hi ? (blk + hb - hi) * TPB : 0;
     s0 = 0;
   }
-  const int64_t ntiles = L;
+  const int ntiles = L;
   const uint16_t* __restrict__ Xs = args.Xs;
   const float* __restrict__ invs = args.invs;
   const int32_t* __restrict__ perm = args.perm;
@@ -421,58 +425,67 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
     goff[u] = r * DP + c8 * 8;
     loff[u] = r * LDR + c8 * 8;
   }
-  u32x4 pre[CPT];   // a native vector type: the HIP uint4 struct keeps this array out of registers
-  float pre_inv = 0.0f;
-  int pre_perm = -1;
-  float pre_tmn = INFINITY;
-  float pre_thr = INFINITY;
-  float pre_tthr = INFINITY;
+  // Two register sets of prefetched tiles (a native vector type: the HIP uint4 struct keeps
+  // such arrays out of registers).  Set s holds the tiles of steps s+1, s+3, ...: step t commits
+  // set t&1 to LDS and reloads it with tile t+3, so each load has two steps to arrive.
+  u32x4 pre[2][CPT];
+  float pre_inv[2], pre_tmn[2], pre_thr[2], pre_tthr[2];
+  int pre_perm[2];
   // tile of step t of this workgroup's scan: ws + ((s0 + t) mod L), taken mod ntp.  Every step
-  // prefetches and commits a tile (the last step re-loads its own tile into the idle buffer):
-  // with no conditional load the compiler needs no wait for stale loads at the loop head.
+  // prefetches and commits a tile (past the end the last tile is loaded again, into a buffer no
+  // one reads): with no conditional load the compiler needs no wait for stale loads.
 #define KNN_TILE_AT(t)                                                                        \
-  ([&](int64_t t_) {                                                                          \
-    int64_t u_ = s0 + t_;                                                                     \
+  ([&](int t_) {                                                                          \
+    int u_ = s0 + t_;                                                                         \
     if (u_ >= L) u_ -= L;                                                                     \
     u_ += ws;                                                                                 \
     return u_ >= ntp ? u_ - ntp : u_;                                                         \
   })(t)
-#define KNN_PREFETCH(tt)                                                                      \
+#define KNN_STEP_CLAMP(x) ((x) < L ? (x) : (L > 0 ? L - 1 : 0))
+#define KNN_PREFETCH(S, tt)                                                                   \
   {                                                                                           \
-    const int64_t tt_ = (tt);                                                                 \
-    pre_tmn = tile_min[tt_];                                                                  \
-    if (SYM) pre_tthr = args.tile_thr[tt_];                                                   \
-    if (TAU) pre_tthr = args.tile_cinv[tt_];                                                  \
+    const int tt_ = (tt);                                                                     \
+    pre_tmn[S] = tile_min[tt_];                                                               \
+    if (SYM) pre_tthr[S] = args.tile_thr[tt_];                                                \
+    if (TAU) pre_tthr[S] = args.tile_cinv[tt_];                                               \
     const uint16_t* src_ = Xs + tt_ * (int64_t)(BT_C * DP);                                   \
-    _Pragma("unroll") for (int u = 0; u < CPT; u++) pre[u] = *(const u32x4*)(src_ + goff[u]); \
-    const int64_t r_ = tt_ * BT_C + (tid & (BT_C - 1));                                       \
-    pre_inv = invs[r_];                                                                       \
-    pre_perm = perm[r_];                                                                      \
-    if (SYM) pre_thr = args.colthr[r_];                                                       \
+    _Pragma("unroll") for (int u = 0; u < CPT; u++) pre[S][u] = *(const u32x4*)(src_ + goff[u]); \
+    const int r_ = tt_ * BT_C + (tid & (BT_C - 1));                                           \
+    pre_inv[S] = invs[r_];                                                                    \
+    pre_perm[S] = perm[r_];                                                                   \
+    if (SYM) pre_thr[S] = args.colthr[r_];                                                    \
   }
-#define KNN_COMMIT(b)                                                                         \
+#define KNN_COMMIT(S, b)                                                                      \
   {                                                                                           \
     const int b_ = (b);                                                                       \
     uint16_t* dst_ = tileb + b_ * BT_C * LDR;                                                 \
-    _Pragma("unroll") for (int u = 0; u < CPT; u++) *(u32x4*)(dst_ + loff[u]) = pre[u];       \
+    _Pragma("unroll") for (int u = 0; u < CPT; u++) *(u32x4*)(dst_ + loff[u]) = pre[S][u];    \
     if (tid < BT_C) {                                                                         \
-      tinv[b_ * BT_C + tid] = pre_inv;                                                        \
-      tperm[b_ * BT_C + tid] = pre_perm;                                                      \
-      if (SYM) tthr[b_ * BT_C + tid] = pre_thr;                                               \
+      tinv[b_ * BT_C + tid] = pre_inv[S];                                                     \
+      tperm[b_ * BT_C + tid] = pre_perm[S];                                                   \
+      if (SYM) tthr[b_ * BT_C + tid] = pre_thr[S];                                            \
     }                                                                                         \
     if (tid == 0) {                                                                           \
-      tmn[b_] = pre_tmn;                                                                      \
-      if (SYM || TAU) tmn[2 + b_] = pre_tthr;                                                 \
+      tmn[b_] = pre_tmn[S];                                                                   \
+      if (SYM || TAU) tmn[2 + b_] = pre_tthr[S];                                              \
     }                                                                                         \
   }
 
-  KNN_PREFETCH(KNN_TILE_AT(0));
-  KNN_COMMIT(0);
+  // step 0's tile to buffer 0; the tiles of steps 1 and 2 in flight
+  KNN_PREFETCH(0, KNN_TILE_AT(0));
+  KNN_COMMIT(0, 0);
+  KNN_PREFETCH(0, KNN_TILE_AT(KNN_STEP_CLAMP(1)));
+  KNN_PREFETCH(1, KNN_TILE_AT(KNN_STEP_CLAMP(2)));
   __syncthreads();
 
-  for (int64_t t = 0; t < ntiles; t++) {
-    const int buf = NBUF == 2 ? (int)(t & 1) : 0;
-    KNN_PREFETCH(KNN_TILE_AT(t + 1 < ntiles ? t + 1 : t));
+  // steps in pairs, so that register set s of step t = t0 + s is a compile-time index; an odd
+  // last step is followed by one whose epilogue is skipped
+  int t0 = 0;
+  // the step body, inlined twice per pass of the loop below with its register set s fixed
+  auto step = [&](auto s_tag) __attribute__((always_inline)) {
+    constexpr int s = decltype(s_tag)::value;
+    const int t = t0 + s;
+    const int buf = NBUF == 2 ? s : 0;
 
     f32x16 acc[2][NQB];
 #pragma unroll
@@ -499,8 +512,9 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
     }
 
     // ---- epilogue: filter, then exact insertion for the rare hits
+    if (t < ntiles) {
     const float mn = tmn[buf];
-    const int64_t tcur_tile = SYM ? KNN_TILE_AT(t) : 0;
+    const int tcur_tile = SYM ? KNN_TILE_AT(t) : 0;
 #pragma unroll
     for (int qb = 0; qb < NQB; qb++) {
       float m = -INFINITY;
@@ -509,22 +523,30 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
 #pragma unroll
         for (int i = 0; i < 16; i++) m = fmaxf(m, acc[cb][qb][i]);
       if (TAU) {
-        // bound scores a * c, c the tile's smallest 1/|x_j|: for a > 0 no larger than the
-        // list score a / |x_j| (rounding is monotone); the lane keeps its TAU_T largest
+        // the lane keeps the TAU_T largest list scores a / |x_j| (a > 0) it sees; a * c, c the
+        // tile's smallest 1/|x_j|, is no larger (rounding is monotone) and screens candidates
+        // before 1/|x_j| is read
         const float c = tmn[2 + buf];
         if (__ballot(m * c > rt[qb][TAU_T - 1])) {
 #pragma unroll
           for (int cb = 0; cb < 2; cb++)
 #pragma unroll
-            for (int i = 0; i < 16; i++) {
-              const float av = acc[cb][qb][i];
-              float x = av * c;
-              if (av > 0.0f && x > rt[qb][TAU_T - 1]) {
+            for (int g = 0; g < 4; g++) {
+              const float g4 = fmaxf(fmaxf(acc[cb][qb][4 * g], acc[cb][qb][4 * g + 1]),
+                                     fmaxf(acc[cb][qb][4 * g + 2], acc[cb][qb][4 * g + 3]));
+              if (g4 * c > rt[qb][TAU_T - 1]) {
 #pragma unroll
-                for (int j = 0; j < TAU_T; j++) {
-                  const float hi = fmaxf(rt[qb][j], x);
-                  x = fminf(rt[qb][j], x);
-                  rt[qb][j] = hi;
+                for (int r = 0; r < 4; r++) {
+                  const float av = acc[cb][qb][4 * g + r];
+                  float x = av * tinv[buf * BT_C + cb * 32 + 8 * g + 4 * half + r];
+                  if (av > 0.0f && av * c > rt[qb][TAU_T - 1] && x > rt[qb][TAU_T - 1]) {
+#pragma unroll
+                    for (int j = 0; j < TAU_T; j++) {
+                      const float hi = fmaxf(rt[qb][j], x);
+                      x = fminf(rt[qb][j], x);
+                      rt[qb][j] = hi;
+                    }
+                  }
                 }
               }
             }
@@ -548,19 +570,29 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
             // a candidate can enter only if its raw score reaches the tile bound fth (fth is at
             // most the list's worst score times the smallest candidate norm of the tile), so the
             // norm and index of a candidate are read only when that test passes
+            // groups of 4 candidates are skipped whole when their largest score misses fth
 #pragma unroll
             for (int cb = 0; cb < 2; cb++) {
 #pragma unroll
-              for (int i = 0; i < 16; i++) {
-                const float a = acc[cb][qb][i];
-                if (a >= fth) {
-                  const int cl = buf * BT_C + cb * 32 + 8 * (i / 4) + 4 * half + (i % 4);
-                  const float iv = tinv[cl];
-                  const int jp = tperm[cl];
-                  const float sc = a * iv;
-                  if (iv > 0.0f && jp != qi && better<float>(sc, jp, tcur, tcur_i)) {
-                    list_replace_worst(ls, li, KPP, sc, jp, tcur, tcur_i, wslot);
-                    changed = true;
+              for (int g = 0; g < 4; g++) {
+                const float g4 = fmaxf(fmaxf(acc[cb][qb][4 * g], acc[cb][qb][4 * g + 1]),
+                                       fmaxf(acc[cb][qb][4 * g + 2], acc[cb][qb][4 * g + 3]));
+                if (g4 >= fth) {
+#pragma unroll
+                  for (int r = 0; r < 4; r++) {
+                    const int i = 4 * g + r;
+                    const float a = acc[cb][qb][i];
+                    if (a >= fth) {
+                      const int cl = buf * BT_C + cb * 32 + 8 * g + 4 * half + r;
+                      const float iv = tinv[cl];
+                      const int jp = tperm[cl];
+                      const float sc = a * iv;
+                      // below the bound tq no candidate can end in the list
+                      if (iv > 0.0f && jp != qi && sc >= tq[qb] && better<float>(sc, jp, tcur, tcur_i)) {
+                        list_replace_worst(ls, li, KPP, sc, jp, tcur, tcur_i, wslot);
+                        changed = true;
+                      }
+                    }
                   }
                 }
               }
@@ -627,14 +659,21 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
       }
     }
 
+    }  // t < ntiles
+
     if (NBUF == 2) {
-      KNN_COMMIT(buf ^ 1);
+      KNN_COMMIT(s, buf ^ 1);
       __syncthreads();
     } else {
       __syncthreads();            // every wave is done with the single buffer
-      KNN_COMMIT(0);
+      KNN_COMMIT(s, 0);
       __syncthreads();
     }
+    KNN_PREFETCH(s, KNN_TILE_AT(KNN_STEP_CLAMP(t + 3)));
+  };
+  for (; t0 < ntiles; t0 += 2) {
+    step(std::integral_constant<int, 0>{});
+    step(std::integral_constant<int, 1>{});
   }
 
   if (TAU) {
@@ -679,6 +718,7 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
 }
 
 #undef KNN_TILE_AT
+#undef KNN_STEP_CLAMP
 #undef KNN_PREFETCH
 #undef KNN_COMMIT
 

@@ -722,6 +722,11 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
 #undef KNN_PREFETCH
 #undef KNN_COMMIT
 
+__global__ void fill_i64_kernel(int64_t* __restrict__ a, int64_t count, int64_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) a[i] = v;
+}
+
 // smallest candidate-side threshold of each tile
 __global__ void tile_thr_kernel(const float* __restrict__ colthr, int64_t ntp, float* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -731,15 +736,23 @@ __global__ void tile_thr_kernel(const float* __restrict__ colthr, int64_t ntp, f
   out[t] = m;
 }
 
+// first hand-over entry of each row in the sorted keys (rows without entries keep -1)
+__global__ void handover_starts_kernel(const uint64_t* __restrict__ hkey, int64_t hn, int64_t* __restrict__ start) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= hn) return;
+  if (e == 0 || hkey[e] != hkey[e - 1]) start[hkey[e]] = e;
+}
+
 // Final lists: row p's list (sorted best first) merged with the hand-over entries of row p
-// (hkey sorted, hn entries), then written at the original index with scores scaled by 1/|x_p|
-// to cosines.  One thread per row; the result is the top KP of the union under the (score,
-// index) order, whatever order the entries arrive in.
+// (hkey sorted, hn entries, the first at start[p]), then written at the original index with
+// scores scaled by 1/|x_p| to cosines.  One thread per row; the result is the top KP of the
+// union under the (score, index) order, whatever order the entries arrive in.
 __global__ __launch_bounds__(256) void knn_merge_kernel(int64_t n, int KP, const int32_t* __restrict__ lidx,
                                                         const float* __restrict__ lsim, const float* __restrict__ invs,
                                                         const int32_t* __restrict__ perm,
                                                         const uint64_t* __restrict__ hkey,
                                                         const uint64_t* __restrict__ hval, int64_t hn,
+                                                        const int64_t* __restrict__ start,
                                                         int32_t* __restrict__ cand_idx, float* __restrict__ cand_sim) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int KPP = (KP + 3) & ~3;
@@ -753,16 +766,11 @@ __global__ __launch_bounds__(256) void knn_merge_kernel(int64_t n, int KP, const
     li[r] = r < KP ? lidx[p * KP + r] : -1;
     if (r < KP && li[r] == INT_MAX && wp == KP - 1 && r < KP - 1) wp = r;
   }
-  if (hn > 0) {
+  const int64_t e0 = hn > 0 ? start[p] : -1;
+  if (e0 >= 0) {
     float ws = ls[wp];
     int wj = li[wp];
-    int64_t lo = 0, hi = hn;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (hkey[mid] < (uint64_t)p) lo = mid + 1;
-      else hi = mid;
-    }
-    for (int64_t e = lo; e < hn && hkey[e] == (uint64_t)p; e++) {
+    for (int64_t e = e0; e < hn && hkey[e] == (uint64_t)p; e++) {
       const uint64_t v = hval[e];
       const float s = __uint_as_float((uint32_t)(v & 0xffffffffu));
       const int j = (int)(v >> 32);
@@ -1338,6 +1346,7 @@ ancka_status bf16_scan(ancka_ctx* ctx, int DP, ScanArgs args, const std::vector<
   hipEvent_t* ev = nullptr;
   ST_TRY(ctx_events(ctx, &ev));
   int64_t hn = 0;
+  int64_t* hstart = nullptr;
   bool timed_sym = false;
   if (args.w >= 0 && args.tau) ST_TRY(run_bf16<SCAN_TAU>(ctx, DP, args));
   ST_TRY(run_bf16<SCAN_WIN>(ctx, DP, args));
@@ -1360,9 +1369,17 @@ ancka_status bf16_scan(ancka_ctx* ctx, int DP, ScanArgs args, const std::vector<
       if (st) st->rescanned = 1;
     } else {
       hn = (int64_t)hc;
+      const int64_t npad = args.nwg * 4 * bf16_qw(DP);
       int bits = 1;
-      while (bits < 63 && ((int64_t)1 << bits) < args.nwg * 4 * bf16_qw(DP)) bits++;
+      while (bits < 63 && ((int64_t)1 << bits) < npad) bits++;
       ST_TRY(radix_sort_u64(ctx, args.hkey, args.hval, hn, bits));
+      ST_TRY(ws_get_t(ctx, "knn_hstart", (size_t)npad, &hstart));
+      fill_i64_kernel<<<(unsigned)cdiv(npad, 256), 256, 0, ctx->stream>>>(hstart, npad, -1);
+      LAUNCH_CHECK(ctx);
+      if (hn > 0) {
+        handover_starts_kernel<<<(unsigned)cdiv(hn, 256), 256, 0, ctx->stream>>>(args.hkey, hn, hstart);
+        LAUNCH_CHECK(ctx);
+      }
     }
   }
   const int KPP = (args.KP + 3) & ~3;
@@ -1373,7 +1390,7 @@ ancka_status bf16_scan(ancka_ctx* ctx, int DP, ScanArgs args, const std::vector<
     mattr = true;
   }
   knn_merge_kernel<<<(unsigned)cdiv(n, 256), 256, (size_t)256 * KPP * 8, ctx->stream>>>(
-      n, args.KP, args.lidx, args.lsim, args.invs, args.perm, args.hkey, args.hval, hn, cidx, csim);
+      n, args.KP, args.lidx, args.lsim, args.invs, args.perm, args.hkey, args.hval, hn, hstart, cidx, csim);
   LAUNCH_CHECK(ctx);
   if (st) {
     int32_t wmax = -1;

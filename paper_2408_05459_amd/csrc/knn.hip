@@ -194,21 +194,25 @@ __global__ __launch_bounds__(256) void knn_vector_kernel(const TX* __restrict__ 
 }
 
 // ---- BF16 MFMA tiles ------------------------------------------------------------------------
-// Scan order.  Rows are grouped into coarse cells (the most similar of NPIV pivot rows) and
-// sub-cells; queries and candidates share this order (a bf16 copy Xs, padded to whole blocks of
-// QB = 4*QW rows).  Workgroup I owns block I of QB consecutive queries.
+// Scan order.  Rows are grouped into coarse cells (the most similar of NPIV pivot rows), in
+// norm order inside a cell; queries and candidates share this order (a bf16 copy Xs, padded to
+// whole blocks of QB = 4*QW rows).  Workgroup I owns block I of QB consecutive queries, and its
+// window is a block range lo .. hi around I (the blocks of the cells its rows belong to), with
+// J in I's window exactly when I is in J's.
 // Two passes cover every unordered pair of rows.
-//  Window pass: block I scans the tiles of blocks I-w .. I+w (cyclically), starting at its own
-//    sub-cell; the most similar rows lie there, so each list ends close to its final state.
-//  Symmetric pass: block I scans blocks I+w+1 .. I+h (h = half the ring; for an even block count
-//    the opposite block is scanned only from the lower half), so each remaining pair of blocks
-//    meets once.  A tile score a = x_i.x_j serves both rows: the query side updates the lists
+//  Window pass: block I scans the tiles of its window, starting at its own cell; the most
+//    similar rows lie there, so each list ends close to its final state.  A bound pass over the
+//    same tiles first finds a lower bound of each query's KP-th score, where its list starts.
+//  Symmetric pass: block I scans blocks hi+1 .. I+h (h = half the ring; for an even block count
+//    the opposite block is scanned only from the lower half), so each pair of blocks outside
+//    each other's windows meets once.  A tile score a = x_i.x_j serves both rows: the query side updates the lists
 //    of block I in LDS as in the window pass; on the candidate side, a pair whose score reaches
 //    the candidate row's threshold after the window pass (the worst entry of its list then)
 //    is handed over through a global buffer and merged into that row's list afterwards.  The
 //    candidate-side test is a necessary condition for entering the final list, so the merged
 //    lists equal those of a full scan of all pairs.
-// With w >= the ring's half the window pass is the whole scan and the symmetric pass is skipped.
+// When a window would exceed a quarter of the ring the window pass is the whole scan and the
+// symmetric pass is skipped.
 // The order changes nothing in the result (lists are ordered by the (similarity, index) key).
 // Tiles.  Wave w holds its QW queries as MFMA B operands in registers for the whole kernel;
 // 64-row candidate tiles (two 32-row A blocks) stream through double-buffered LDS.
@@ -266,7 +270,7 @@ struct ScanArgs {
   const float* invs;         // [npad] 1/|x|, 0 for zero and padding rows
   const int32_t* perm;       // [npad] original index, -1 for padding rows
   const float* tile_min;     // [ntp] smallest norm of a non-zero row of each tile (+inf if none)
-  const int32_t* wg_start;   // [nwg] first tile of each block's own sub-cell
+  const int32_t* wg_start;   // [nwg] first tile of the cell of each block's first row
   int64_t nwg;               // blocks of QB rows (workgroups)
   int64_t ntp;               // tiles in the padded ring, nwg * QB / BT_C
   int w;                     // -1: the window is the whole ring (no symmetric pass); else >= 0
@@ -360,6 +364,8 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
   float tq[NQB];     // window pass: the bound pass's lower bound, a floor for the threshold
   float colq[NQB];   // symmetric pass: 1/|x_i| of the lane's query (0: the query takes no part)
   float rt[NQB][TAU_T];  // bound pass: the lane's TAU_T largest bound scores, descending
+  float wv[NQB];     // worst entry of the query's list: score, index, slot (both halves hold it)
+  int wi[NQB], wp[NQB];
   int qloc[NQB];
   int qorig[NQB];
   // Xs, invs and perm are padded with zero rows (invs 0, perm -1) to whole workgroups, so no
@@ -374,6 +380,10 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
     tq[qb] = (MODE == SCAN_WIN && args.tau) ? args.tau[qs] : -INFINITY;
     thr[qb] = iq > 0.0f ? (SYM ? lwv[qloc[qb]] : tq[qb]) : INFINITY;
     colq[qb] = iq;
+    // (the bound pass has no lists: its LDS holds only the tiles)
+    wv[qb] = TAU ? -INFINITY : lwv[qloc[qb]];
+    wi[qb] = TAU ? INT_MAX : lwi[qloc[qb]];
+    wp[qb] = TAU ? 0 : lwp[qloc[qb]];
 #pragma unroll
     for (int j = 0; j < TAU_T; j++) rt[qb][j] = -INFINITY;
 #pragma unroll
@@ -563,10 +573,9 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
         int* li = lidx + q * KPP;
         for (int h = 0; h < 2; h++) {
           if (hit && half == h) {
-            float tcur = lwv[q];
-            int tcur_i = lwi[q];
-            int wslot = lwp[q];
-            bool changed = false;
+            float tcur = wv[qb];
+            int tcur_i = wi[qb];
+            int wslot = wp[qb];
             // a candidate can enter only if its raw score reaches the tile bound fth (fth is at
             // most the list's worst score times the smallest candidate norm of the tile), so the
             // norm and index of a candidate are read only when that test passes
@@ -588,27 +597,34 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
                       const int jp = tperm[cl];
                       const float sc = a * iv;
                       // below the bound tq no candidate can end in the list
-                      if (iv > 0.0f && jp != qi && sc >= tq[qb] && better<float>(sc, jp, tcur, tcur_i)) {
+                      if (iv > 0.0f && jp != qi && sc >= tq[qb] && better<float>(sc, jp, tcur, tcur_i))
                         list_replace_worst(ls, li, KPP, sc, jp, tcur, tcur_i, wslot);
-                        changed = true;
-                      }
                     }
                   }
                 }
               }
             }
-            if (changed) {
-              lwv[q] = tcur;
-              lwi[q] = tcur_i;
-              lwp[q] = wslot;
+            wv[qb] = tcur;
+            wi[qb] = tcur_i;
+            wp[qb] = wslot;
+          }
+          // the two halves of the wave update the same lists in turn; the other half's lanes
+          // take over the worst-entry record (lane l and l ^ 32 hold the same query).  LDS
+          // operations of one wave execute in program order, so only the compiler must keep
+          // them in order; a memory fence here would also wait for the next tile's global loads.
+          {
+            const float ov = __shfl_xor(wv[qb], 32, ANCKA_WAVE);
+            const int oi = __shfl_xor(wi[qb], 32, ANCKA_WAVE);
+            const int op = __shfl_xor(wp[qb], 32, ANCKA_WAVE);
+            if (half != h) {
+              wv[qb] = ov;
+              wi[qb] = oi;
+              wp[qb] = op;
             }
           }
-          // the two halves of the wave update the same lists in turn.  LDS operations of one
-          // wave execute in program order, so only the compiler must keep them in order; a
-          // memory fence here would also wait for the next tile's global loads in flight.
           asm volatile("" ::: "memory");
         }
-        if (thr[qb] != INFINITY) thr[qb] = fmaxf(lwv[q], tq[qb]);
+        if (thr[qb] != INFINITY) thr[qb] = fmaxf(wv[qb], tq[qb]);
       }
       if (SYM) {
         // candidate side: the lane's query i is a candidate of the 32 tile rows j it holds
@@ -713,7 +729,13 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
       args.lidx[qs * KP + r] = li[r];
       args.lsim[qs * KP + r] = ls[r];
     }
-    if (!SYM) args.colthr[qs] = invs[qs] > 0.0f ? (li[KP - 1] != INT_MAX ? ls[KP - 1] : -INFINITY) : INFINITY;
+    // the worst entry of a full list, at least the bound of the bound pass: both are lower bounds
+    // of the row's final KP-th score
+    if (!SYM) {
+      const float lw = li[KP - 1] != INT_MAX ? ls[KP - 1] : -INFINITY;
+      const float tb = args.tau ? args.tau[qs] : -INFINITY;
+      args.colthr[qs] = invs[qs] > 0.0f ? fmaxf(lw, tb) : INFINITY;
+    }
   }
 }
 
@@ -1018,66 +1040,8 @@ __global__ void cell_starts_kernel(const uint64_t* __restrict__ keys, int64_t n,
   cs[c] = lo;
 }
 
-// Second level of the scan order: each row of cell c (sorted positions cs[c] .. cs[c+1]) takes the
-// most similar of NPIV sub-pivots, the rows at evenly spaced positions of its cell (ties to the
-// smaller sub-pivot).  key2 = c << 6 | sub.  Block (x, c) handles 256 consecutive rows of cell c.
-template <typename TX>
-__global__ __launch_bounds__(256) void subcell_assign_kernel(const TX* __restrict__ X, int64_t d, int64_t ldx,
-                                                             const float* __restrict__ invn,
-                                                             const int64_t* __restrict__ cs,
-                                                             const uint64_t* __restrict__ order,
-                                                             uint64_t* __restrict__ key2) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int c = blockIdx.y;
-  const int64_t c0 = cs[c], size = cs[c + 1] - c0;
-  const int64_t p0 = c0 + (int64_t)blockIdx.x * 256;
-  if (p0 >= c0 + size) return;
-  const int dp = (int)((d + 7) / 8 * 8);
-  uint16_t* P = (uint16_t*)smem;            // [NPIV][dp]
-  float* pinv = (float*)(P + NPIV * dp);    // [NPIV]
-  for (int e = threadIdx.x; e < NPIV * dp; e += 256) {
-    const int s = e / dp, col = e % dp;
-    const int64_t row = (int64_t)order[c0 + (int64_t)s * size / NPIV];
-    P[e] = (col < d) ? f32_to_bf16_rne((float)load_as_double<TX>(X, row * ldx + col)) : (uint16_t)0;
-  }
-  if (threadIdx.x < NPIV) pinv[threadIdx.x] = invn[order[c0 + (int64_t)threadIdx.x * size / NPIV]];
-  __syncthreads();
-  const int64_t p = p0 + threadIdx.x;
-  if (p >= c0 + size) return;
-  const TX* xr = X + (int64_t)order[p] * ldx;
-  float acc[NPIV];
-#pragma unroll
-  for (int s = 0; s < NPIV; s++) acc[s] = 0.0f;
-  for (int col0 = 0; col0 < dp; col0 += 8) {
-    float xv[8];
-#pragma unroll
-    for (int u = 0; u < 8; u++) xv[u] = (col0 + u < d) ? (float)load_as_double<TX>(xr, col0 + u) : 0.0f;
-#pragma unroll
-    for (int s = 0; s < NPIV; s++) {
-      const uint4 pv = *(const uint4*)(P + s * dp + col0);
-      const uint32_t w[4] = {pv.x, pv.y, pv.z, pv.w};
-#pragma unroll
-      for (int u = 0; u < 4; u++) {
-        acc[s] = fmaf(xv[2 * u], __uint_as_float(w[u] << 16), acc[s]);
-        acc[s] = fmaf(xv[2 * u + 1], __uint_as_float(w[u] & 0xffff0000u), acc[s]);
-      }
-    }
-  }
-  int best = 0;
-  float bv = acc[0] * pinv[0];
-#pragma unroll
-  for (int s = 1; s < NPIV; s++) {
-    const float v = acc[s] * pinv[s];
-    if (v > bv) {
-      bv = v;
-      best = s;
-    }
-  }
-  key2[p] = ((uint64_t)c << 6) | (uint64_t)best;
-}
-
-// first tile of each workgroup's scan: the tile holding the first row of the group (cell, or
-// cell and sub-cell) of its first query; the group is the sorted key shifted right by `shift`
+// first tile of each workgroup's scan: the tile holding the first row of the group of its first
+// query (the cell: the sorted key shifted right by `shift`)
 __global__ void wg_start_kernel(const uint64_t* __restrict__ keys, int64_t n, int qb, int64_t nwg, int shift,
                                 int32_t* __restrict__ start) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1534,9 +1498,8 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
           (const uint16_t*)(const void*)X, n, d, ldx, invn, piv, keys, nrm, order);
       LAUNCH_CHECK(ctx);
       ST_TRY(radix_sort_u64(ctx, keys, order, n, 40));
-      // second level: rows of a cell grouped by the nearest of NPIV sub-pivots of that cell, the
-      // norm order kept inside a group (stable sort on the 12-bit group key); a workgroup starts
-      // its scan at its own group, whose rows are the likeliest neighbours of its queries
+      // cell ranges of the scan order (rows of a cell in norm order: a 64-row tile then spans a
+      // narrow band of norms, which keeps the tile filters tight)
       int64_t* cstart = nullptr;
       ST_TRY(ws_get_t(ctx, "knn_cstart", NPIV + 1, &cstart));
       cell_starts_kernel<<<1, 128, 0, ctx->stream>>>(keys, n, cstart);
@@ -1544,18 +1507,6 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
       int64_t hcs[NPIV + 1];
       HIP_TRY(ctx, hipMemcpyAsync(hcs, cstart, sizeof(hcs), hipMemcpyDeviceToHost, ctx->stream));
       HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-      int64_t maxc = 1;
-      for (int c = 0; c < NPIV; c++) maxc = (hcs[c + 1] - hcs[c]) > maxc ? (hcs[c + 1] - hcs[c]) : maxc;
-      static bool sattr = false;
-      if (!sattr) {
-        HIP_TRY(ctx, hipFuncSetAttribute((const void*)subcell_assign_kernel<uint16_t>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        sattr = true;
-      }
-      subcell_assign_kernel<uint16_t><<<dim3((unsigned)cdiv(maxc, 256), NPIV), 256, csm, ctx->stream>>>(
-          (const uint16_t*)(const void*)X, d, ldx, invn, cstart, order, keys);
-      LAUNCH_CHECK(ctx);
-      ST_TRY(radix_sort_u64(ctx, keys, order, n, 12));
       gather_sorted_kernel<<<(unsigned)cdiv(npad, 4), 256, 0, ctx->stream>>>((const uint16_t*)(const void*)X, n, npad,
                                                                              d, ldx, order, invn, DP, Xs, invs, perm);
       LAUNCH_CHECK(ctx);
@@ -1563,7 +1514,7 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
       ST_TRY(ws_get_t(ctx, "knn_tcinv", (size_t)nt, &tcinv));
       tile_min_sorted_kernel<<<(unsigned)cdiv(nt, 256), 256, 0, ctx->stream>>>(invs, n, BT_C, tmin, tcinv, nt);
       LAUNCH_CHECK(ctx);
-      wg_start_kernel<<<(unsigned)cdiv(nwg, 256), 256, 0, ctx->stream>>>(keys, n, QB, nwg, 0, wgs);
+      wg_start_kernel<<<(unsigned)cdiv(nwg, 256), 256, 0, ctx->stream>>>(keys, n, QB, nwg, 32, wgs);
       LAUNCH_CHECK(ctx);
       ScanArgs sa{};
       sa.Xs = Xs;
@@ -1576,6 +1527,7 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
       std::vector<int32_t> hlo, hhi;
       sa.w = scan_windows(n, nwg, QB, hcs, hlo, hhi) ? 0 : -1;
       sa.KP = KP;
+
       ST_TRY(ws_get_t(ctx, "knn_lidx", (size_t)npad * KP, &sa.lidx));
       ST_TRY(ws_get_t(ctx, "knn_lsim", (size_t)npad * KP, &sa.lsim));
       ST_TRY(ws_get_t(ctx, "knn_colthr", (size_t)npad, &sa.colthr));

@@ -119,6 +119,15 @@ __global__ void row_argmax_kernel(const T* __restrict__ P, int64_t n, int k, int
   labels[i] = b;
 }
 
+// the non-zero of each row of F(0) = alpha Yh: alpha / sqrt(|C_l|) (the expression of mhc_f0_kernel)
+template <typename T>
+__global__ void mhc_f0v_kernel(T* __restrict__ v, int64_t n, const int32_t* __restrict__ labels,
+                               const int32_t* __restrict__ counts, T alpha) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  v[i] = alpha / sqrt((T)counts[labels[i]]);
+}
+
 // F(0) = alpha Yh
 template <typename T>
 __global__ void mhc_f0_kernel(T* __restrict__ F, int64_t n, int64_t ld, const int32_t* __restrict__ labels,
@@ -218,10 +227,13 @@ ancka_status init_bcm_typed(ancka_ctx* ctx, const ancka_op* op, int k, double al
   T *P0 = nullptr, *P1 = nullptr;
   ST_TRY(ws_get_t(ctx, "ib_P0", (size_t)n * ld, &P0));
   ST_TRY(ws_get_t(ctx, "ib_P1", (size_t)n * ld, &P1));
-  init_pi_kernel<T><<<nb256(n), 256, 0, ctx->stream>>>(P0, n, ld, centre_of, (T)alpha);
-  LAUNCH_CHECK(ctx);
+  // Pi(0) = alpha Z0 is one-hot: the first step reads it through centre_of
+  if (T_i == 0) {
+    init_pi_kernel<T><<<nb256(n), 256, 0, ctx->stream>>>(P0, n, ld, centre_of, (T)alpha);
+    LAUNCH_CHECK(ctx);
+  }
   for (int t = 0; t < T_i; t++) {
-    ST_TRY(op_apply_init(ctx, op, P0, P1, k, ld, alpha, centre_of));
+    ST_TRY(op_apply_init(ctx, op, t == 0 ? nullptr : P0, P1, k, ld, alpha, centre_of));
     std::swap(P0, P1);
   }
   row_argmax_kernel<T><<<nb256(n), 256, 0, ctx->stream>>>(P0, n, k, ld, labels);
@@ -256,10 +268,18 @@ ancka_status mhc_typed(ancka_ctx* ctx, const ancka_op* op, const int32_t* labels
   ST_TRY(ws_get_t(ctx, "mhc_F0", (size_t)n * ld, &F0));
   ST_TRY(ws_get_t(ctx, "mhc_F1", (size_t)n * ld, &F1));
   ST_TRY(ws_get_t(ctx, "mhc_part", (size_t)cdiv(n, 256), &part));
-  mhc_f0_kernel<T><<<nb256(n), 256, 0, ctx->stream>>>(F0, n, ld, labels, counts, (T)alpha);
+  // F(0) = alpha Yh is one-hot: the first product reads it through the labels and the value
+  // alpha / sqrt(|C_l|) of each row
+  T* f0v = nullptr;
+  ST_TRY(ws_get_t(ctx, "mhc_f0v", (size_t)n, &f0v));
+  mhc_f0v_kernel<T><<<nb256(n), 256, 0, ctx->stream>>>(f0v, n, labels, counts, (T)alpha);
   LAUNCH_CHECK(ctx);
+  if (gamma == 0) {
+    mhc_f0_kernel<T><<<nb256(n), 256, 0, ctx->stream>>>(F0, n, ld, labels, counts, (T)alpha);
+    LAUNCH_CHECK(ctx);
+  }
   for (int l = 0; l < gamma; l++) {
-    ST_TRY(op_apply_mhc(ctx, op, F0, F1, k, ld, alpha, labels, counts));
+    ST_TRY(op_apply_mhc(ctx, op, l == 0 ? nullptr : F0, F1, k, ld, alpha, labels, counts, f0v));
     std::swap(F0, F1);
   }
   mhc_trace_kernel<T><<<nb256(n), 256, 0, ctx->stream>>>(F0, n, ld, labels, counts, part);

@@ -122,7 +122,7 @@ ancka_status cell_order(ancka_ctx* ctx, const void* X, int xdtype, int64_t n, in
 ancka_status op_apply(ancka_ctx* ctx, const ancka_op* op, const void* Q, void* Z, int cols, int64_t ld);
 // Z = (1-alpha) P Q + alpha * Yh(labels) (MHC recursion step; Yh from labels and counts).
 ancka_status op_apply_mhc(ancka_ctx* ctx, const ancka_op* op, const void* Q, void* Z, int cols, int64_t ld,
-                          double alpha, const int32_t* labels, const int32_t* counts);
+                          double alpha, const int32_t* labels, const int32_t* counts, const void* f0val = nullptr);
 // Pi^T <- (1-alpha) P_N^T Pi^T + alpha Z0^T on the topology walk (InitBCM step).
 ancka_status op_apply_init(ancka_ctx* ctx, const ancka_op* op, const void* Pin, void* Pout, int cols,
                            int64_t ld, double alpha, const int32_t* centres);

@@ -82,22 +82,49 @@ struct SpmmArgs {
   const int32_t* counts;   // EPI_MHC: cluster sizes
   T b;
   const int32_t* rorder;   // nullable: output row handled by slot w is rorder[w]
+  // nullable: the sources ksrc and ssrc (and tsrc when oh_t) are one-hot blocks given by their
+  // labels: row j holds oh_val[j] (oh_alpha when oh_val is null) in column oh_lab[j] and zeros
+  // elsewhere (oh_lab[j] < 0: a zero row).  The products then read a label and a value per
+  // gathered row instead of the row, with the same arithmetic: the skipped terms are exact zeros.
+  const int32_t* oh_lab;
+  const T* oh_val;
+  T oh_alpha;
+  int oh_t;
 };
+
+// row j of a one-hot source, the lanes' W columns from coff
+template <typename T>
+__device__ __forceinline__ void onehot_row(const int32_t* __restrict__ lab, const T* __restrict__ val, T alpha,
+                                           int64_t j, int coff, T (&v)[V16<T>::W]) {
+  constexpr int W = V16<T>::W;
+  const int l = lab[j];
+  const T x = val ? val[j] : alpha;
+#pragma unroll
+  for (int c = 0; c < W; c++) v[c] = (coff + c == l) ? x : (T)0;
+}
 
 template <typename T, int LPR>
 __device__ __forceinline__ void gather_segment(const int64_t beg, const int64_t end, const int32_t* __restrict__ idx,
                                                const T* __restrict__ colw, int colw_stride, int colw_off,
                                                const T* __restrict__ vals, const T* __restrict__ src, int64_t ld,
-                                               int sub, bool col_ok, int coff, T (&acc)[V16<T>::W]) {
+                                               int sub, bool col_ok, int coff, T (&acc)[V16<T>::W],
+                                               const int32_t* __restrict__ olab, const T* __restrict__ oval,
+                                               T oalpha) {
   constexpr int W = V16<T>::W;
   for (int64_t p0 = beg; p0 < end; p0 += LPR) {
     const int64_t myp = p0 + sub;
     int32_t jm = 0;
     T wm = (T)0;
+    int32_t lm = -1;   // one-hot source: label and value of row jm, loaded by the lane that owns jm
+    T xm = (T)0;
     if (myp < end) {
       jm = idx[myp];
       wm = vals ? vals[myp] : (T)1;
       if (colw) wm *= colw[(int64_t)jm * colw_stride + colw_off];
+      if (olab) {
+        lm = olab[jm];
+        xm = oval ? oval[jm] : oalpha;
+      }
     }
     const int cnt = (int)((end - p0) < LPR ? (end - p0) : LPR);
     int u = 0;
@@ -105,14 +132,22 @@ __device__ __forceinline__ void gather_segment(const int64_t beg, const int64_t 
       int32_t j[4];
       T w[4];
       T v[4][W];
+      int l[4];
+      T x[4];
 #pragma unroll
       for (int q = 0; q < 4; q++) {
+        // every lane of the group takes part in the broadcasts (no shuffle under a lane branch)
         j[q] = __shfl(jm, u + q, LPR);
         w[q] = __shfl(wm, u + q, LPR);
+        l[q] = olab ? __shfl(lm, u + q, LPR) : -1;
+        x[q] = olab ? __shfl(xm, u + q, LPR) : (T)0;
       }
 #pragma unroll
       for (int q = 0; q < 4; q++) {
-        if (col_ok) vload<T>(src + (int64_t)j[q] * ld + coff, v[q]);
+        if (col_ok && olab) {
+#pragma unroll
+          for (int c = 0; c < W; c++) v[q][c] = (coff + c == l[q]) ? x[q] : (T)0;
+        } else if (col_ok) vload<T>(src + (int64_t)j[q] * ld + coff, v[q]);
         else {
 #pragma unroll
           for (int c = 0; c < W; c++) v[q][c] = (T)0;
@@ -126,9 +161,16 @@ __device__ __forceinline__ void gather_segment(const int64_t beg, const int64_t 
     for (; u < cnt; u++) {
       const int32_t j = __shfl(jm, u, LPR);
       const T w = __shfl(wm, u, LPR);
+      const int l = olab ? __shfl(lm, u, LPR) : -1;
+      const T x = olab ? __shfl(xm, u, LPR) : (T)0;
       T v[W];
       if (col_ok) {
-        vload<T>(src + (int64_t)j * ld + coff, v);
+        if (olab) {
+#pragma unroll
+          for (int c = 0; c < W; c++) v[c] = (coff + c == l) ? x : (T)0;
+        } else {
+          vload<T>(src + (int64_t)j * ld + coff, v);
+        }
 #pragma unroll
         for (int c = 0; c < W; c++) acc[c] = fma(w, v[c], acc[c]);
       }
@@ -157,20 +199,22 @@ __global__ __launch_bounds__(256) void spmm_kernel(const SpmmArgs<T> A) {
     T part[W];
 #pragma unroll
     for (int c = 0; c < W; c++) part[c] = (T)0;
-    gather_segment<T, LPR>(b, e, A.tidx, A.tcol, A.segs, l, nullptr, A.tsrc, A.tld, sub, col_ok, coff, part);
+    gather_segment<T, LPR>(b, e, A.tidx, A.tcol, A.segs, l, nullptr, A.tsrc, A.tld, sub, col_ok, coff, part,
+                           A.oh_t ? A.oh_lab : nullptr, A.oh_val, A.oh_alpha);
     const T s = A.tscale ? A.tscale[seg] : (T)1;
 #pragma unroll
     for (int c = 0; c < W; c++) acc[c] = fma(s, part[c], acc[c]);
   }
   if (A.kptr) {
     gather_segment<T, LPR>(A.kptr[r], A.kptr[r + 1], A.kidx, nullptr, 0, 0, A.kval, A.ksrc, A.ld, sub, col_ok, coff,
-                           acc);
+                           acc, A.oh_lab, A.oh_val, A.oh_alpha);
   }
-  if (A.ssrc && col_ok) {
+  if ((A.ssrc || A.oh_lab) && col_ok && (A.self || A.selfu != (T)0)) {
     const T sc = A.self ? A.self[r] : A.selfu;
     if (sc != (T)0) {
       T v[W];
-      vload<T>(A.ssrc + r * A.ld + coff, v);
+      if (A.oh_lab) onehot_row<T>(A.oh_lab, A.oh_val, A.oh_alpha, r, coff, v);
+      else vload<T>(A.ssrc + r * A.ld + coff, v);
 #pragma unroll
       for (int c = 0; c < W; c++) acc[c] = fma(sc, v[c], acc[c]);
     }
@@ -239,15 +283,22 @@ SpmmArgs<T> blank(int64_t rows, T* out, int64_t ld, int cols) {
   A.counts = nullptr;
   A.b = (T)0;
   A.rorder = nullptr;
+  A.oh_lab = nullptr;
+  A.oh_val = nullptr;
+  A.oh_alpha = (T)0;
+  A.oh_t = 0;
   return A;
 }
 
 // P Q with optional epilogue (EPI_NONE: plain; EPI_MHC: (1-alpha) P F + alpha Yh)
+// (Q null: the source is the one-hot block of oh_lab / oh_val / oh_alpha)
 template <typename T>
 ancka_status apply_typed(ancka_ctx* ctx, const ancka_op* op, const T* Q, T* Z, int cols, int64_t ld, T a, int epi,
-                         const int32_t* labels, const int32_t* counts, T b) {
+                         const int32_t* labels, const int32_t* counts, T b, const int32_t* oh_lab = nullptr,
+                         const T* oh_val = nullptr, T oh_alpha = (T)0) {
   const int64_t n = op->n;
   const T* topo_src = Q;
+  bool topo_onehot = oh_lab != nullptr;
   if (op->kind == ANCKA_HYPERGRAPH) {
     T* E = nullptr;
     ST_TRY(ws_get_t(ctx, "spmm_E", (size_t)op->m * ld, &E));
@@ -256,8 +307,13 @@ ancka_status apply_typed(ancka_ctx* ctx, const ancka_op* op, const T* Q, T* Z, i
     S1.tidx = op->eidx;
     S1.tscale = (const T*)op->escale;
     S1.tsrc = Q;
+    S1.oh_lab = oh_lab;
+    S1.oh_val = oh_val;
+    S1.oh_alpha = oh_alpha;
+    S1.oh_t = 1;
     ST_TRY(launch_spmm<T>(ctx, S1));
     topo_src = E;
+    topo_onehot = false;
   }
   SpmmArgs<T> S = blank<T>(n, Z, ld, cols);
   S.segs = op->kind == ANCKA_HYPERGRAPH ? 1 : op->L;
@@ -277,13 +333,19 @@ ancka_status apply_typed(ancka_ctx* ctx, const ancka_op* op, const T* Q, T* Z, i
   S.labels = labels;
   S.counts = counts;
   S.b = b;
+  S.oh_lab = oh_lab;
+  S.oh_val = oh_val;
+  S.oh_alpha = oh_alpha;
+  S.oh_t = topo_onehot ? 1 : 0;
   return launch_spmm<T>(ctx, S);
 }
 
+// (Pin null: the source is one-hot, alpha in column centre_of[j] of the centres' rows)
 template <typename T>
 ancka_status init_typed(ancka_ctx* ctx, const ancka_op* op, const T* Pin, T* Pout, int cols, int64_t ld, T a,
                         const int32_t* centre_of, T b) {
   const int64_t n = op->n;
+  const int32_t* oh = Pin ? nullptr : centre_of;
   if (op->kind == ANCKA_HYPERGRAPH) {
     T* E = nullptr;
     ST_TRY(ws_get_t(ctx, "spmm_E", (size_t)op->m * ld, &E));
@@ -293,6 +355,9 @@ ancka_status init_typed(ancka_ctx* ctx, const ancka_op* op, const T* Pin, T* Pou
     S1.tscale = (const T*)op->escale;
     S1.tcol = (const T*)op->tcol;   // 1/delta(v) of the source node
     S1.tsrc = Pin;
+    S1.oh_lab = oh;
+    S1.oh_alpha = b;
+    S1.oh_t = 1;
     ST_TRY(launch_spmm<T>(ctx, S1));
     SpmmArgs<T> S2 = blank<T>(n, Pout, ld, cols);
     S2.tptr = op->tptr;
@@ -312,6 +377,9 @@ ancka_status init_typed(ancka_ctx* ctx, const ancka_op* op, const T* Pin, T* Pou
   S.tidx = op->tidx;
   S.tcol = (const T*)op->tcol;      // 1/(L_j deg_l(j)) of the source node in layer l
   S.tsrc = Pin;
+  S.oh_lab = oh;
+  S.oh_alpha = b;
+  S.oh_t = 1;
   S.a = a;
   S.epi = EPI_INIT;
   S.labels = centre_of;
@@ -328,12 +396,13 @@ ancka_status op_apply(ancka_ctx* ctx, const ancka_op* op, const void* Q, void* Z
 }
 
 ancka_status op_apply_mhc(ancka_ctx* ctx, const ancka_op* op, const void* Q, void* Z, int cols, int64_t ld,
-                          double alpha, const int32_t* labels, const int32_t* counts) {
+                          double alpha, const int32_t* labels, const int32_t* counts, const void* f0val) {
+  // Q null: the source is F(0) = alpha Yh, row j holding f0val[j] in column labels[j]
   if (op->dtype == ANCKA_F64)
     return apply_typed<double>(ctx, op, (const double*)Q, (double*)Z, cols, ld, 1.0 - alpha, EPI_MHC, labels, counts,
-                               alpha);
+                               alpha, Q ? nullptr : labels, (const double*)f0val, alpha);
   return apply_typed<float>(ctx, op, (const float*)Q, (float*)Z, cols, ld, (float)(1.0 - alpha), EPI_MHC, labels,
-                            counts, (float)alpha);
+                            counts, (float)alpha, Q ? nullptr : labels, (const float*)f0val, (float)alpha);
 }
 
 ancka_status op_apply_init(ancka_ctx* ctx, const ancka_op* op, const void* Pin, void* Pout, int cols, int64_t ld,

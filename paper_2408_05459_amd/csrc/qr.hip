@@ -166,11 +166,30 @@ __global__ __launch_bounds__(256) void chol_kernel(const double* __restrict__ Gi
 }
 
 // Q[i, :] = Z[i, :] R^-1 in FP64 arithmetic; dq partial = sum ||Q_i - Qprev_i||^2 per block.
+// 16-byte vector of T
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float4 type; static constexpr int W = 4; };
+template <> struct Vec16<double> { typedef double2 type; static constexpr int W = 2; };
+
+template <typename T>
+__device__ __forceinline__ T vget(const typename Vec16<T>::type& v, int i);
+template <>
+__device__ __forceinline__ float vget<float>(const float4& v, int i) {
+  return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+template <>
+__device__ __forceinline__ double vget<double>(const double2& v, int i) {
+  return i == 0 ? v.x : v.y;
+}
+
+// Q = Z R^{-1} row by row in FP64 (one thread per row).  With vec, rows are read (Z and Q(t-1))
+// and written (whole vectors below kp) in 16-byte vectors: ld is then a multiple of the vector
+// width, at least KPM, and the base pointers are 16-byte aligned.
 template <typename T, int KPM>
 __global__ __launch_bounds__(256) void apply_rinv_kernel(const T* __restrict__ Z, T* __restrict__ Q, int64_t n, int kp,
                                                          int64_t ld, const double* __restrict__ Rinv,
                                                          const T* __restrict__ Qprev, double* __restrict__ dq_part,
-                                                         const int* __restrict__ active) {
+                                                         const int* __restrict__ active, int vec) {
   if (active && *active == 0) return;
   __shared__ double Rs[KPM][KPM + 1];
   __shared__ double red[256];
@@ -182,7 +201,51 @@ __global__ __launch_bounds__(256) void apply_rinv_kernel(const T* __restrict__ Z
   __syncthreads();
   const int64_t r = (int64_t)blockIdx.x * 256 + tid;
   double dq = 0.0;
-  if (r < n) {
+  if (r < n && vec) {
+    typedef typename Vec16<T>::type VT;
+    constexpr int VW = Vec16<T>::W;
+    double z[KPM];
+#pragma unroll
+    for (int c0 = 0; c0 < KPM; c0 += VW) {
+      const VT v = *(const VT*)(Z + r * ld + c0);
+#pragma unroll
+      for (int u = 0; u < VW; u++) z[c0 + u] = (c0 + u < kp) ? (double)vget<T>(v, u) : 0.0;
+    }
+#pragma unroll
+    for (int j0 = 0; j0 < KPM; j0 += VW) {
+      T qv[VW];
+#pragma unroll
+      for (int u = 0; u < VW; u++) {
+        const int j = j0 + u;
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c <= j; c++) s = fma(z[c], Rs[c][j], s);
+        qv[u] = (T)s;
+      }
+      if (j0 < kp) {
+        if (Qprev) {
+          const VT pv = *(const VT*)(Qprev + r * ld + j0);
+#pragma unroll
+          for (int u = 0; u < VW; u++)
+            if (j0 + u < kp) {
+              const double dd = (double)qv[u] - (double)vget<T>(pv, u);
+              dq = fma(dd, dd, dq);
+            }
+        }
+        if (j0 + VW <= kp) {
+          VT o;
+          T* op = (T*)&o;
+#pragma unroll
+          for (int u = 0; u < VW; u++) op[u] = qv[u];
+          *(VT*)(Q + r * ld + j0) = o;
+        } else {
+#pragma unroll
+          for (int u = 0; u < VW; u++)
+            if (j0 + u < kp) Q[r * ld + j0 + u] = qv[u];
+        }
+      }
+    }
+  } else if (r < n) {
     double z[KPM];
 #pragma unroll
     for (int c = 0; c < KPM; c++) z[c] = (c < kp) ? (double)Z[r * ld + c] : 0.0;
@@ -244,14 +307,18 @@ template <typename T>
 ancka_status launch_apply(ancka_ctx* ctx, const T* Z, T* Q, int64_t n, int kp, int64_t ld, const double* Rinv,
                           const T* Qprev, double* dq_part, const int* active) {
   const unsigned grid = (unsigned)cdiv(n, 256);
+  const int kpm = kp <= 8 ? 8 : kp <= 16 ? 16 : kp <= 32 ? 32 : 64;
+  const int vw = 16 / (int)sizeof(T);
+  const auto al16 = [](const void* p) { return p == nullptr || ((uintptr_t)p % 16) == 0; };
+  const int vec = (ld % vw == 0 && ld >= kpm && al16(Z) && al16(Q) && al16(Qprev)) ? 1 : 0;
   if (kp <= 8)
-    apply_rinv_kernel<T, 8><<<grid, 256, 0, ctx->stream>>>(Z, Q, n, kp, ld, Rinv, Qprev, dq_part, active);
+    apply_rinv_kernel<T, 8><<<grid, 256, 0, ctx->stream>>>(Z, Q, n, kp, ld, Rinv, Qprev, dq_part, active, vec);
   else if (kp <= 16)
-    apply_rinv_kernel<T, 16><<<grid, 256, 0, ctx->stream>>>(Z, Q, n, kp, ld, Rinv, Qprev, dq_part, active);
+    apply_rinv_kernel<T, 16><<<grid, 256, 0, ctx->stream>>>(Z, Q, n, kp, ld, Rinv, Qprev, dq_part, active, vec);
   else if (kp <= 32)
-    apply_rinv_kernel<T, 32><<<grid, 256, 0, ctx->stream>>>(Z, Q, n, kp, ld, Rinv, Qprev, dq_part, active);
+    apply_rinv_kernel<T, 32><<<grid, 256, 0, ctx->stream>>>(Z, Q, n, kp, ld, Rinv, Qprev, dq_part, active, vec);
   else
-    apply_rinv_kernel<T, 64><<<grid, 256, 0, ctx->stream>>>(Z, Q, n, kp, ld, Rinv, Qprev, dq_part, active);
+    apply_rinv_kernel<T, 64><<<grid, 256, 0, ctx->stream>>>(Z, Q, n, kp, ld, Rinv, Qprev, dq_part, active, vec);
   LAUNCH_CHECK(ctx);
   return ANCKA_OK;
 }

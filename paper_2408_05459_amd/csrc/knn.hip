@@ -778,16 +778,29 @@ __global__ __launch_bounds__(256) void knn_merge_kernel(int64_t n, int KP, const
                                                         int32_t* __restrict__ cand_idx, float* __restrict__ cand_sim) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int KPP = (KP + 3) & ~3;
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (p >= n) return;   // no barrier below: each thread works on its own slice of LDS
-  float* ls = (float*)smem + threadIdx.x * KPP;
-  int* li = (int*)((float*)smem + 256 * KPP) + threadIdx.x * KPP;
-  int wp = KP - 1;
-  for (int r = 0; r < KPP; r++) {
-    ls[r] = r < KP ? lsim[p * KP + r] : INFINITY;
-    li[r] = r < KP ? lidx[p * KP + r] : -1;
-    if (r < KP && li[r] == INT_MAX && wp == KP - 1 && r < KP - 1) wp = r;
+  const int64_t p0 = (int64_t)blockIdx.x * 256;
+  const int64_t p = p0 + threadIdx.x;
+  float* lsb = (float*)smem;
+  int* lib = (int*)((float*)smem + 256 * KPP);
+  // the block's 256 lists are contiguous: load them into LDS with consecutive threads on
+  // consecutive entries
+  const int64_t rows = (n - p0) < 256 ? (n - p0) : 256;
+  for (int e = threadIdx.x; e < 256 * KPP; e += 256) {
+    const int row = e / KPP, r = e % KPP;
+    const bool in = row < rows && r < KP;
+    lsb[e] = in ? lsim[(p0 + row) * KP + r] : INFINITY;
+    lib[e] = in ? lidx[(p0 + row) * KP + r] : -1;
   }
+  __syncthreads();
+  if (p >= n) return;   // no barrier below: each thread works on its own slice of LDS
+  float* ls = lsb + threadIdx.x * KPP;
+  int* li = lib + threadIdx.x * KPP;
+  int wp = KP - 1;
+  for (int r = 0; r < KP - 1; r++)
+    if (li[r] == INT_MAX) {
+      wp = r;
+      break;
+    }
   const int64_t e0 = hn > 0 ? start[p] : -1;
   if (e0 >= 0) {
     float ws = ls[wp];
@@ -1109,15 +1122,33 @@ __global__ __launch_bounds__(256) void knn_rescore_kernel(const TX* __restrict__
   int my_j = INT_MAX;
   int valid = 0;
   const double sqi = sq[i];
-  for (int r = 0; r < KP; r++) {
-    const int j = cand_idx[i * KP + r];
-    if (j < 0) continue;
-    valid++;
-    const double dot = exact_dot<TX>(X, ldx, d, i, j, lane);
-    const double s = dot / sqrt(sqi * sq[j]);
-    if (lane == r) {
-      my_s = s;
-      my_j = j;
+  const TX* xi = X + i * ldx;
+  // four candidates at a time, so that their row gathers and reductions overlap; each dot is
+  // accumulated exactly as exact_dot does (lane order over d, then the butterfly)
+  for (int r0 = 0; r0 < KP; r0 += 4) {
+    int jj[4];
+    double acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      jj[q] = (r0 + q < KP) ? cand_idx[i * KP + r0 + q] : -1;
+      acc[q] = 0.0;
+    }
+    for (int64_t c = lane; c < d; c += ANCKA_WAVE) {
+      const double a = load_as_double<TX>(xi, c);
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (jj[q] >= 0) acc[q] += a * load_as_double<TX>(X + (int64_t)jj[q] * ldx, c);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const double dot = wave_sum(acc[q]);
+      if (jj[q] < 0) continue;
+      valid++;
+      const double s = dot / sqrt(sqi * sq[jj[q]]);
+      if (lane == r0 + q) {
+        my_s = s;
+        my_j = jj[q];
+      }
     }
   }
   wave_sort_desc(my_s, my_j, lane);

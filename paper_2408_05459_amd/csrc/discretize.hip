@@ -29,7 +29,10 @@ struct DiscState {
   double obj_prev;
 };
 
-template <typename T, int KM>
+// OFF = 0 or 1: the rows of Q are read in 16-byte vectors from Q - OFF (16-byte aligned, ldq a
+// multiple of the vector width, OFF + k <= ldq; the block's first column is then usually the
+// column before Q); OFF = -1: element by element.
+template <typename T, int KM, int OFF>
 __global__ __launch_bounds__(256) void disc_pass_kernel(const T* __restrict__ Q, int64_t n, int k, int64_t ldq,
                                                         const T* __restrict__ R, int32_t* __restrict__ labels,
                                                         unsigned long long* __restrict__ Sg,
@@ -51,11 +54,37 @@ __global__ __launch_bounds__(256) void disc_pass_kernel(const T* __restrict__ Q,
   if (i < n) {
     T q[KM];
     double nr = 0.0;
+    // (the last row is read element by element: its vectors could run past the rows' k columns
+    // to the end of ldq, which a caller's buffer need not hold for the last row)
+    if (OFF >= 0 && i + 1 < n) {
+      constexpr int W = 16 / sizeof(T);
+      constexpr int OF = OFF >= 0 ? OFF : 0;
+      constexpr int NV = (KM + OF + W - 1) / W;
+      T raw[NV * W];
+      const T* base = Q - OF + i * ldq;
 #pragma unroll
-    for (int c = 0; c < KM; c++) {
-      q[c] = (c < k) ? Q[i * ldq + c] : (T)0;
-      nr += (double)q[c] * (double)q[c];
+      for (int v = 0; v < NV; v++) {
+        if (v * W < OF + k) {
+          if constexpr (W == 4) {
+            const float4 x = *(const float4*)(base + v * W);
+            raw[v * W] = x.x; raw[v * W + 1] = x.y; raw[v * W + 2] = x.z; raw[v * W + 3] = x.w;
+          } else {
+            const double2 x = *(const double2*)(base + v * W);
+            raw[v * W] = x.x; raw[v * W + 1] = x.y;
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < W; u++) raw[v * W + u] = (T)0;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < KM; c++) q[c] = (c < k) ? raw[c + OF] : (T)0;
+    } else {
+#pragma unroll
+      for (int c = 0; c < KM; c++) q[c] = (c < k) ? Q[i * ldq + c] : (T)0;
     }
+#pragma unroll
+    for (int c = 0; c < KM; c++) nr += (double)q[c] * (double)q[c];
     if (nr > 0.0) {
       const T inv = (T)(1.0 / sqrt(nr));
 #pragma unroll
@@ -309,9 +338,17 @@ ancka_status disc_launch(ancka_ctx* ctx, const T* Q, int64_t n, int k, int64_t l
   disc_init_kernel<T><<<16, 256, 0, ctx->stream>>>(k, Rd, Rt, st, Sg, cg);
   LAUNCH_CHECK(ctx);
   const unsigned grid = (unsigned)cdiv(n, 256);
+  // vector reads from Q - voff when that is 16-byte aligned (voff = 0 or 1 columns back)
+  int voff = -1;
+  const int64_t vw = 16 / (int64_t)sizeof(T);
+  if (ldq % vw == 0)
+    for (int o = 0; o <= 1 && voff < 0; o++)
+      if (((uintptr_t)(Q - o) % 16) == 0 && o + k <= ldq) voff = o;
   DiscState hs{0, 0, 0.0, 0.0};
   for (int it = 0; it < max_iter; it++) {
-    disc_pass_kernel<T, KM><<<grid, 256, 0, ctx->stream>>>(Q, n, k, ldq, Rt, labels, Sg, cg, st);
+    if (voff == 0) disc_pass_kernel<T, KM, 0><<<grid, 256, 0, ctx->stream>>>(Q, n, k, ldq, Rt, labels, Sg, cg, st);
+    else if (voff == 1) disc_pass_kernel<T, KM, 1><<<grid, 256, 0, ctx->stream>>>(Q, n, k, ldq, Rt, labels, Sg, cg, st);
+    else disc_pass_kernel<T, KM, -1><<<grid, 256, 0, ctx->stream>>>(Q, n, k, ldq, Rt, labels, Sg, cg, st);
     LAUNCH_CHECK(ctx);
     disc_svd_kernel<T, KM><<<1, 256, 0, ctx->stream>>>(Sg, cg, k, n, Rd, Rt, st);
     LAUNCH_CHECK(ctx);

@@ -201,7 +201,9 @@ __global__ __launch_bounds__(256) void apply_rinv_kernel(const T* __restrict__ Z
   __syncthreads();
   const int64_t r = (int64_t)blockIdx.x * 256 + tid;
   double dq = 0.0;
-  if (r < n && vec) {
+  // (the last row goes element by element: its vectors could run past kp to the end of ld, which
+  // a caller's buffer need not hold for the last row)
+  if (r + 1 < n && vec) {
     typedef typename Vec16<T>::type VT;
     constexpr int VW = Vec16<T>::W;
     double z[KPM];

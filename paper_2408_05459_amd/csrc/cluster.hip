@@ -409,63 +409,108 @@ ancka_status cluster_loop(ancka_ctx* ctx, const ancka_op* op, const ancka_params
   ph[warm ? ANCKA_PHASE_WARM : ANCKA_PHASE_INIT] += now_ms() - t0;
 
   // ---- main loop (Alg. 4, main loop)
+  // The iterations run on the main stream in blocks of tau.  At a check t the block Q(t) is
+  // copied aside; unless Eq. (tcond-1) already ends the run, the next block is queued on the
+  // main stream at once, and the Discretize and MHC of check t run on the side stream meanwhile
+  // (the next iterations need only Q(t)).  Results, checks and stopping points are those of
+  // running everything in order; a check that could end the run is not overlapped.
+  hipStream_t main_s = ctx->stream, side_s = nullptr;
+  hipEvent_t snap_ev = nullptr;
+  ST_TRY(ctx_side_stream(ctx, &side_s, &snap_ev));
+  void* Qs = nullptr;
+  ST_TRY(ws_get(ctx, "cl_Qs", (size_t)n * ldq * es, &Qs));
   double best_phi = phi0;
   int best_t = 0;
   std::vector<double> hist{phi0};
   trace(0, phi0);
   int reason = ANCKA_STOP_MAX_ITER;
   int t = 0;
-  double ti = now_ms();   // start of the current block of tau iterations
-  for (t = 1; t <= p.T_a; t++) {
-    const bool check = (t % p.tau) == 0;
-    ST_TRY(op_apply(ctx, op, Q, Z, k + 1, ldq));
-    ST_TRY(qr_block(ctx, p.q_dtype, Z, Qn, n, k + 1, ldq, check ? Q : nullptr, check ? dq2 : nullptr, nullptr));
-    std::swap(Q, Qn);
-    if (!check) continue;
+  int enq = 0;   // iterations queued on the main stream
+  auto queue_to = [&](int upto) -> ancka_status {
+    for (; enq < upto;) {
+      enq++;
+      const bool check = (enq % p.tau) == 0;
+      ST_TRY(op_apply(ctx, op, Q, Z, k + 1, ldq));
+      ST_TRY(qr_block(ctx, p.q_dtype, Z, Qn, n, k + 1, ldq, check ? Q : nullptr, check ? dq2 : nullptr, nullptr));
+      std::swap(Q, Qn);
+    }
+    return ANCKA_OK;
+  };
+  double ti = now_ms();   // start of the current wait for the main stream
+  ST_TRY(queue_to(p.T_a < p.tau ? p.T_a : p.tau));
+  for (int tc = p.tau;; tc += p.tau) {
+    if (tc > p.T_a) {   // no check left: the trailing iterations, then stop at T_a
+      ST_TRY(queue_to(p.T_a));
+      HIP_TRY(ctx, hipStreamSynchronize(main_s));
+      ph[ANCKA_PHASE_ITER] += now_ms() - ti;
+      t = p.T_a;
+      break;
+    }
     double hdq2 = 0.0;
     int hflags[4] = {0, 0, 0, 0};
-    HIP_TRY(ctx, hipMemcpyAsync(&hdq2, dq2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(hflags, qflags, sizeof(hflags), hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(&hdq2, dq2, sizeof(double), hipMemcpyDeviceToHost, main_s));
+    HIP_TRY(ctx, hipMemcpyAsync(hflags, qflags, sizeof(hflags), hipMemcpyDeviceToHost, main_s));
+    HIP_TRY(ctx, hipStreamSynchronize(main_s));
     ph[ANCKA_PHASE_ITER] += now_ms() - ti;
-    if (hflags[1] & 2) return set_err(ctx, ANCKA_ERR_NUMERICAL, "ancka_cluster: Cholesky QR broke down at t=%d", t);
-    // Discretize columns 2..k+1 (the constant eigenvector is dropped)
+    if (hflags[1] & 2) return set_err(ctx, ANCKA_ERR_NUMERICAL, "ancka_cluster: Cholesky QR broke down at t=%d", tc);
+    const bool converged = p.early_stop && sqrt(hdq2) < p.eps_q;
+    // Q(t) aside, then the next block of iterations (not when this check ends the run)
+    HIP_TRY(ctx, hipMemcpyAsync(Qs, Q, (size_t)n * ldq * es, hipMemcpyDeviceToDevice, main_s));
+    HIP_TRY(ctx, hipEventRecord(snap_ev, main_s));
+    ti = now_ms();
+    // Eq. (tcond-2) can end the run at this check only if the conductance already rose at the
+    // previous one; the next block is queued ahead only when this check cannot end the run
+    const size_t hn = hist.size();
+    const bool may_stop = converged || (p.early_stop && hn >= 2 && hist[hn - 2] < hist[hn - 1]);
+    if (!may_stop) ST_TRY(queue_to(tc + p.tau <= p.T_a ? tc + p.tau : p.T_a));
+    // Discretize columns 2..k+1 (the constant eigenvector is dropped), then MHC, on the side
+    HIP_TRY(ctx, hipStreamWaitEvent(side_s, snap_ev, 0));
+    ctx->stream = side_s;
     double td = now_ms();
     int32_t dit = 0;
-    ST_TRY(discretize_internal(ctx, (const char*)Q + es, p.q_dtype, n, k, ldq, p.disc_max_iter, ycur, nullptr, nullptr,
-                               &dit));
-    R->disc_iters_total += dit;
-    ph[ANCKA_PHASE_DISCRETIZE] += now_ms() - td;
-    double tm = now_ms();
     double phi = 0.0;
-    ST_TRY(mhc_host(ctx, op, ycur, k, p.alpha, p.gamma, &phi));
+    ancka_status st = discretize_internal(ctx, (const char*)Qs + es, p.q_dtype, n, k, ldq, p.disc_max_iter, ycur,
+                                          nullptr, nullptr, &dit);
+    double tm = now_ms();
+    if (st == ANCKA_OK) st = mhc_host(ctx, op, ycur, k, p.alpha, p.gamma, &phi);
+    if (st == ANCKA_OK && phi < best_phi) {
+      copy_i32_kernel<<<nb256(n), 256, 0, side_s>>>(ycur, ybest, n);
+      if (hipGetLastError() != hipSuccess) st = set_err(ctx, ANCKA_ERR_HIP, "ancka_cluster: launch failed");
+    }
+    ctx->stream = main_s;
+    if (st != ANCKA_OK) {
+      (void)hipStreamSynchronize(main_s);
+      return st;
+    }
+    R->disc_iters_total += dit;
+    ph[ANCKA_PHASE_DISCRETIZE] += tm - td;
     ph[ANCKA_PHASE_MHC] += now_ms() - tm;
-    trace(t, phi);
+    trace(tc, phi);
     if (phi < best_phi) {
       best_phi = phi;
-      best_t = t;
-      copy_i32_kernel<<<nb256(n), 256, 0, ctx->stream>>>(ycur, ybest, n);
-      LAUNCH_CHECK(ctx);
+      best_t = tc;
     }
     hist.push_back(phi);
-    ti = now_ms();
+    if (converged) {
+      reason = ANCKA_STOP_CONVERGED;
+      t = tc;
+      break;
+    }
     if (p.early_stop) {
-      if (sqrt(hdq2) < p.eps_q) {
-        reason = ANCKA_STOP_CONVERGED;
-        break;
-      }
       const size_t h = hist.size();
       if (h >= 3 && hist[h - 3] < hist[h - 2] && hist[h - 2] < hist[h - 1]) {
         reason = ANCKA_STOP_EARLY;
+        t = tc;
         break;
       }
     }
+    // the run goes on: queue the next block now if it was held back
+    ti = now_ms();
+    if (may_stop) ST_TRY(queue_to(tc + p.tau <= p.T_a ? tc + p.tau : p.T_a));
   }
-  if (t > p.T_a) {
-    t = p.T_a;
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    ph[ANCKA_PHASE_ITER] += now_ms() - ti;
-  }
+  // the side stream's last copy into ybest, and any queued block, finish before the labels
+  HIP_TRY(ctx, hipStreamSynchronize(side_s));
+  HIP_TRY(ctx, hipStreamSynchronize(main_s));
   copy_i32_kernel<<<nb256(n), 256, 0, ctx->stream>>>(ybest, labels, n);
   LAUNCH_CHECK(ctx);
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

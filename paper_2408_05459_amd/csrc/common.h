@@ -29,10 +29,14 @@ struct ancka_ctx {
   std::map<std::string, DevBuf> ws;   // grow-only named workspaces
   hipEvent_t ev[8] = {};               // timing events, created on first use
   bool ev_ready = false;
+  hipStream_t side = nullptr;          // second stream of the clustering loop (default priority)
+  hipEvent_t side_ev = nullptr;        // orders it after the main stream
 };
 
 // the context's timing events (created once)
 ancka_status ctx_events(ancka_ctx* ctx, hipEvent_t** out);
+// the context's second stream and its ordering event (created once)
+ancka_status ctx_side_stream(ancka_ctx* ctx, hipStream_t* s, hipEvent_t* e);
 
 struct ancka_op {
   int kind = 0;

@@ -34,6 +34,16 @@ ancka_status ws_get(ancka_ctx* ctx, const char* name, size_t bytes, void** out) 
   return ANCKA_OK;
 }
 
+ancka_status ctx_side_stream(ancka_ctx* ctx, hipStream_t* s, hipEvent_t* e) {
+  if (!ctx->side) {
+    HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->side_ev, hipEventDisableTiming));
+  }
+  *s = ctx->side;
+  *e = ctx->side_ev;
+  return ANCKA_OK;
+}
+
 ancka_status ctx_events(ancka_ctx* ctx, hipEvent_t** out) {
   if (!ctx->ev_ready) {
     for (auto& e : ctx->ev) HIP_TRY(ctx, hipEventCreate(&e));
@@ -84,6 +94,11 @@ void ancka_destroy(ancka_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipStreamDestroy(ctx->side);
+    (void)hipEventDestroy(ctx->side_ev);
+  }
   for (auto& kv : ctx->ws)
     if (kv.second.ptr) (void)hipFree(kv.second.ptr);
   if (ctx->ev_ready)

@@ -295,13 +295,13 @@ SpmmArgs<T> blank(int64_t rows, T* out, int64_t ld, int cols) {
 template <typename T>
 ancka_status apply_typed(ancka_ctx* ctx, const ancka_op* op, const T* Q, T* Z, int cols, int64_t ld, T a, int epi,
                          const int32_t* labels, const int32_t* counts, T b, const int32_t* oh_lab = nullptr,
-                         const T* oh_val = nullptr, T oh_alpha = (T)0) {
+                         const T* oh_val = nullptr, T oh_alpha = (T)0, const char* ename = "spmm_E") {
   const int64_t n = op->n;
   const T* topo_src = Q;
   bool topo_onehot = oh_lab != nullptr;
   if (op->kind == ANCKA_HYPERGRAPH) {
     T* E = nullptr;
-    ST_TRY(ws_get_t(ctx, "spmm_E", (size_t)op->m * ld, &E));
+    ST_TRY(ws_get_t(ctx, ename, (size_t)op->m * ld, &E));
     SpmmArgs<T> S1 = blank<T>(op->m, E, ld, cols);
     S1.tptr = op->eptr;
     S1.tidx = op->eidx;
@@ -400,9 +400,10 @@ ancka_status op_apply_mhc(ancka_ctx* ctx, const ancka_op* op, const void* Q, voi
   // Q null: the source is F(0) = alpha Yh, row j holding f0val[j] in column labels[j]
   if (op->dtype == ANCKA_F64)
     return apply_typed<double>(ctx, op, (const double*)Q, (double*)Z, cols, ld, 1.0 - alpha, EPI_MHC, labels, counts,
-                               alpha, Q ? nullptr : labels, (const double*)f0val, alpha);
+                               alpha, Q ? nullptr : labels, (const double*)f0val, alpha, "spmm_E_mhc");
   return apply_typed<float>(ctx, op, (const float*)Q, (float*)Z, cols, ld, (float)(1.0 - alpha), EPI_MHC, labels,
-                            counts, (float)alpha, Q ? nullptr : labels, (const float*)f0val, (float)alpha);
+                            counts, (float)alpha, Q ? nullptr : labels, (const float*)f0val, (float)alpha,
+                            "spmm_E_mhc");
 }
 
 ancka_status op_apply_init(ancka_ctx* ctx, const ancka_op* op, const void* Pin, void* Pout, int cols, int64_t ld,

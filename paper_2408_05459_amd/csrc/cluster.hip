@@ -249,9 +249,8 @@ ancka_status init_bcm(ancka_ctx* ctx, const ancka_op* op, int k, double alpha, i
 // phi into a device double (no synchronisation)
 template <typename T>
 ancka_status mhc_typed(ancka_ctx* ctx, const ancka_op* op, const int32_t* labels, int k, double alpha, int gamma,
-                       double* phi_dev, int* bad) {
+                       double* phi_dev, int* bad, bool validate) {
   const int64_t n = op->n;
-  const bool validate = true;
   int32_t* counts = nullptr;
   ST_TRY(ws_get_t(ctx, "mhc_counts", 64, &counts));
   ST_TRY(count_labels(ctx, labels, n, k, counts, bad));
@@ -290,9 +289,9 @@ ancka_status mhc_typed(ancka_ctx* ctx, const ancka_op* op, const int32_t* labels
 }
 
 ancka_status mhc_dev(ancka_ctx* ctx, const ancka_op* op, const int32_t* labels, int k, double alpha, int gamma,
-                     double* phi_dev, int* bad) {
-  if (op->dtype == ANCKA_F64) return mhc_typed<double>(ctx, op, labels, k, alpha, gamma, phi_dev, bad);
-  return mhc_typed<float>(ctx, op, labels, k, alpha, gamma, phi_dev, bad);
+                     double* phi_dev, int* bad, bool validate = true) {
+  if (op->dtype == ANCKA_F64) return mhc_typed<double>(ctx, op, labels, k, alpha, gamma, phi_dev, bad, validate);
+  return mhc_typed<float>(ctx, op, labels, k, alpha, gamma, phi_dev, bad, validate);
 }
 
 ancka_status mhc_host(ancka_ctx* ctx, const ancka_op* op, const int32_t* labels, int k, double alpha, int gamma,
@@ -367,8 +366,30 @@ ancka_status cluster_loop(ancka_ctx* ctx, const ancka_op* op, const ancka_params
   ST_TRY(ws_get_t(ctx, "cl_ybest", (size_t)n, &ybest));
   ST_TRY(init_bcm(ctx, op, k, p.alpha, p.T_i, ybest));
   double phi0 = 0.0;
-  ST_TRY(mhc_host(ctx, op, ybest, k, p.alpha, p.gamma, &phi0));
-  R->phi_init_cold = phi0;
+  hipStream_t side_s = nullptr;
+  hipEvent_t side_ev = nullptr;
+  ST_TRY(ctx_side_stream(ctx, &side_s, &side_ev));
+  double* dphi0 = nullptr;
+  bool phi0_pending = false;
+  if (!zwarm) {
+    // the greedy start's conductance is first needed at the first check: it runs on the side
+    // stream beside the starting block and the first block of iterations
+    int* dbad0 = nullptr;
+    ST_TRY(ws_get_t(ctx, "cl_phi0", 1, &dphi0));
+    ST_TRY(ws_get_t(ctx, "cl_bad0", 4, &dbad0));
+    HIP_TRY(ctx, hipEventRecord(side_ev, ctx->stream));
+    HIP_TRY(ctx, hipStreamWaitEvent(side_s, side_ev, 0));
+    hipStream_t main0 = ctx->stream;
+    ctx->stream = side_s;
+    ancka_status st = fill_zero(ctx, dbad0, 16);
+    if (st == ANCKA_OK) st = mhc_dev(ctx, op, ybest, k, p.alpha, p.gamma, dphi0, dbad0, false);   // labels from init_bcm
+    ctx->stream = main0;
+    ST_TRY(st);
+    phi0_pending = true;
+  } else {
+    ST_TRY(mhc_host(ctx, op, ybest, k, p.alpha, p.gamma, &phi0));
+    R->phi_init_cold = phi0;
+  }
   ph[ANCKA_PHASE_INIT] = now_ms() - t0;
   bool warm = false;
   if (zwarm) {
@@ -414,15 +435,26 @@ ancka_status cluster_loop(ancka_ctx* ctx, const ancka_op* op, const ancka_params
   // main stream at once, and the Discretize and MHC of check t run on the side stream meanwhile
   // (the next iterations need only Q(t)).  Results, checks and stopping points are those of
   // running everything in order; a check that could end the run is not overlapped.
-  hipStream_t main_s = ctx->stream, side_s = nullptr;
-  hipEvent_t snap_ev = nullptr;
-  ST_TRY(ctx_side_stream(ctx, &side_s, &snap_ev));
+  hipStream_t main_s = ctx->stream;
+  hipEvent_t snap_ev = side_ev;
   void* Qs = nullptr;
   ST_TRY(ws_get(ctx, "cl_Qs", (size_t)n * ldq * es, &Qs));
   double best_phi = phi0;
   int best_t = 0;
   std::vector<double> hist{phi0};
-  trace(0, phi0);
+  // the greedy start's conductance from the side stream (before the first check uses it)
+  auto resolve_phi0 = [&]() -> ancka_status {
+    if (!phi0_pending) return ANCKA_OK;
+    HIP_TRY(ctx, hipMemcpyAsync(&phi0, dphi0, sizeof(double), hipMemcpyDeviceToHost, side_s));
+    HIP_TRY(ctx, hipStreamSynchronize(side_s));
+    phi0_pending = false;
+    R->phi_init_cold = phi0;
+    best_phi = phi0;
+    hist[0] = phi0;
+    trace(0, phi0);
+    return ANCKA_OK;
+  };
+  if (!phi0_pending) trace(0, phi0);
   int reason = ANCKA_STOP_MAX_ITER;
   int t = 0;
   int enq = 0;   // iterations queued on the main stream
@@ -446,6 +478,7 @@ ancka_status cluster_loop(ancka_ctx* ctx, const ancka_op* op, const ancka_params
       t = p.T_a;
       break;
     }
+    ST_TRY(resolve_phi0());
     double hdq2 = 0.0;
     int hflags[4] = {0, 0, 0, 0};
     HIP_TRY(ctx, hipMemcpyAsync(&hdq2, dq2, sizeof(double), hipMemcpyDeviceToHost, main_s));
@@ -509,6 +542,7 @@ ancka_status cluster_loop(ancka_ctx* ctx, const ancka_op* op, const ancka_params
     if (may_stop) ST_TRY(queue_to(tc + p.tau <= p.T_a ? tc + p.tau : p.T_a));
   }
   // the side stream's last copy into ybest, and any queued block, finish before the labels
+  ST_TRY(resolve_phi0());
   HIP_TRY(ctx, hipStreamSynchronize(side_s));
   HIP_TRY(ctx, hipStreamSynchronize(main_s));
   copy_i32_kernel<<<nb256(n), 256, 0, ctx->stream>>>(ybest, labels, n);

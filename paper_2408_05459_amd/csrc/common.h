@@ -165,13 +165,3 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 __host__ __device__ static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// The chip deals consecutive workgroups of a launch to its 8 XCDs in turn, and each XCD has its
-// own L2.  xcd_block maps the hardware block index to a logical one so that every XCD runs a
-// contiguous range of logical blocks: neighbouring logical blocks, which read the same data,
-// then share an L2.  A bijection of [0, nblocks).
-constexpr int ANCKA_XCDS = 8;
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
-  const int64_t x = b % ANCKA_XCDS, slot = b / ANCKA_XCDS;
-  const int64_t base = nblocks / ANCKA_XCDS, rem = nblocks % ANCKA_XCDS;
-  return x < rem ? x * (base + 1) + slot : rem * (base + 1) + (x - rem) * base + slot;
-}

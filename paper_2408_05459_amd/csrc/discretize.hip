@@ -6,13 +6,16 @@
 //             are kept in 2^-40 fixed point (|q~_c| <= 1) with 64-bit integer atomics, so
 //             they are exact and independent of the order in which rows arrive.
 //  disc_svd   one workgroup: M = S / count (rows of M are cluster means of q~, i.e. Y~^T Q~ with
-//             the column sums of Y as divisors), a one-sided Jacobi SVD in FP64 (Hestenes),
-//             R = V U^T, obj = n - 2 trace(Omega); sets a device flag when |obj - obj_prev| <=
+//             the column sums of Y as divisors); R = V U^T and trace(Omega) of M = U Omega V^T,
+//             in FP64; obj = n - 2 trace(Omega); sets a device flag when |obj - obj_prev| <=
 //             1e-12 max(1, |obj|).  Later steps see the flag and return at once, so labels
-//             keep the values of the last argmax, as Alg. 5 returns them.
-// Singular vectors of (numerically) zero singular values -- e.g. an empty cluster -- are
-// completed deterministically: each takes the standard basis vector with the largest
-// residual against the columns before it (smaller index on ties), orthogonalised twice.
+//             keep the values of the last argmax, as Alg. 5 returns them.  R is the orthogonal
+//             polar factor of M^T: with every cluster non-empty it comes from a Newton-Schulz
+//             iteration (k x k products), otherwise -- or if that does not converge -- from a
+//             one-sided Jacobi SVD (Hestenes).
+// In the Jacobi SVD, singular vectors of (numerically) zero singular values -- e.g. an empty
+// cluster -- are completed deterministically: each takes the standard basis vector with the
+// largest residual against the columns before it (smaller index on ties), orthogonalised twice.
 #include <cmath>
 #include <vector>
 
@@ -99,6 +102,7 @@ __global__ __launch_bounds__(256) void disc_pass_kernel(const T* __restrict__ Q,
         T t = (T)0;
 #pragma unroll
         for (int c = 0; c < KM; c += VW) {
+          if (c >= k) continue;   // R^T rows are zero beyond column k
           T r[VW];
           if constexpr (VW == 4) {
             const float4 v = *(const float4*)&Rs[j][c];
@@ -179,17 +183,45 @@ __device__ void complete_null_cols(double (*B)[KM + 1], int k, const int* isnull
   }
 }
 
+// Sum and maximum over the 256 threads of a workgroup, the same value in every thread; the wave
+// partials are combined in a fixed order, so repeated runs give the same bits.  red: 4 doubles
+// of LDS.  The maximum keeps a NaN.
+__device__ double block_sum4(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__device__ __forceinline__ double max_nan(double a, double b) { return (a >= b || a != a) ? a : b; }
+
+__device__ double block_max4(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max_nan(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if (lane_id() == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return max_nan(max_nan(red[0], red[1]), max_nan(red[2], red[3]));
+}
+
+constexpr int NS_MAX_ITERS = 100;
+constexpr double NS_TOL = 1e-10;   // max |X^T X - I| before the last update
+
 template <typename T, int KM>
 __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __restrict__ Sg, unsigned int* __restrict__ cg,
                                                        int k, int64_t n, double* __restrict__ Rd, T* __restrict__ Rt,
                                                        DiscState* __restrict__ st) {
   if (st->done) return;
   __shared__ double A[KM][KM + 1];   // A[j][i] = column j of M (then of M V)
-  __shared__ double V[KM][KM + 1];   // V[j][i] = column j of V
+  __shared__ double V[KM][KM + 1];   // V[j][i] = column j of V; X^T X in the Newton-Schulz path
+  __shared__ double Xs[2][KM][KM + 1];
+  __shared__ double red[4];
   __shared__ double sig[KM];
   __shared__ int isnull[KM];
   __shared__ int s_rot;
   const int tid = threadIdx.x;
+  const int empty = __syncthreads_or(tid < k && cg[tid] == 0u);
   // M[c][j] = S[c][j] 2^-40 / count[c]; then clear S and counts for the next step
   for (int e = tid; e < KM * KM; e += 256) {
     const int c = e / KM, j = e % KM;
@@ -206,93 +238,217 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
   for (int e = tid; e < k * k; e += 256) Sg[e] = 0ull;
   if (tid < k) cg[tid] = 0u;
 
-  // one-sided Jacobi on the columns of A (round-robin pairs; k padded to even with a zero column)
-  const int kk = k + (k & 1);
-  const int npairs = kk / 2;
-  const int tpp = 256 / 32;  // 8 threads per pair (npairs <= 32)
-  const int pair = tid / tpp, sub = tid % tpp;
-  for (int sweep = 0; sweep < 40; sweep++) {
-    if (tid == 0) s_rot = 0;
+  // R = V U^T is the orthogonal polar factor of M^T, and trace(Omega) = trace(R M).  With every
+  // cluster non-empty M is (in practice) nonsingular, and the Newton-Schulz iteration
+  // X <- X (3I - X^T X) / 2 from X = M^T / s, s >= sigma_max(M) (singular values in (0, 1]),
+  // converges to that factor: the singular vectors stay, the singular values go to 1 (small ones
+  // grow by half per step, then quadratically).  One update follows the first step with
+  // max |X^T X - I| <= 1e-10.  If it does not get there (a singular M) the one-sided Jacobi SVD
+  // below is used.
+  double ssum = 0.0;
+  bool polar = false;
+  if (!empty) {
+    // each thread owns rows tr + 16 r and columns tc + 16 s (r, s < 4) of the k x k products
+    const int tr = tid >> 4, tc = tid & 15;
+    // g = the thread's 4 x 4 block of X^T X
+    auto gram = [&](double (*X)[KM + 1], double (&g)[4][4]) {
+#pragma unroll
+      for (int r = 0; r < 4; r++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) g[r][c] = 0.0;
+#pragma unroll 2
+      for (int i = 0; i < k; i++) {
+        double xa[4], xb[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          xa[r] = (tr + 16 * r < k) ? X[i][tr + 16 * r] : 0.0;
+          xb[r] = (tc + 16 * r < k) ? X[i][tc + 16 * r] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+          for (int c = 0; c < 4; c++) g[r][c] = fma(xa[r], xb[c], g[r][c]);
+      }
+    };
+    // Scale: sigma_max(M)^2 <= max_a sum_b |(M M^T)_ab| (Gershgorin on the Gram of X = M^T), which
+    // is sharp when the cluster means are near orthogonal, so the iteration starts close to 1.
+    double g[4][4];
+    gram(A, g);
+#pragma unroll
+    for (int r = 0; r < 4; r++)
+#pragma unroll
+      for (int c = 0; c < 4; c++)
+        if (tr + 16 * r < k && tc + 16 * c < k) V[tr + 16 * r][tc + 16 * c] = fabs(g[r][c]);
     __syncthreads();
-    for (int step = 0; step < kk - 1; step++) {
-      if (pair < npairs) {
-        const int m = pair;
-        auto pos = [&](int x) { return x == 0 ? 0 : ((x - 1 + step) % (kk - 1)) + 1; };
-        int p = pos(m), q = pos(kk - 1 - m);
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        double al = 0.0, be = 0.0, ga = 0.0;
-        if (q < k) {
-          for (int i = sub; i < k; i += tpp) {
-            const double x = A[p][i], y = A[q][i];
-            al += x * x;
-            be += y * y;
-            ga += x * y;
-          }
-        }
-        // reduce over the 8 lanes of the pair (consecutive lanes of one wave)
-        for (int o = tpp / 2; o > 0; o >>= 1) {
-          al += __shfl_xor(al, o, tpp);
-          be += __shfl_xor(be, o, tpp);
-          ga += __shfl_xor(ga, o, tpp);
-        }
-        if (q < k && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = sgn1(zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t);
-          const double s = c * t;
-          for (int i = sub; i < k; i += tpp) {
-            const double x = A[p][i], y = A[q][i];
-            A[p][i] = c * x - s * y;
-            A[q][i] = s * x + c * y;
-            const double vx = V[p][i], vy = V[q][i];
-            V[p][i] = c * vx - s * vy;
-            V[q][i] = s * vx + c * vy;
-          }
-          if (sub == 0) s_rot = 1;
-        }
+    double rs = 0.0;
+    if (tid < k)
+      for (int b = 0; b < k; b++) rs += V[tid][b];
+    const double bnd = block_max4(rs, red);
+    if (bnd > 0.0) {
+      const double inv = 1.0 / sqrt(bnd);
+      for (int e = tid; e < KM * KM; e += 256) {
+        const int a = e / KM, b = e % KM;
+        Xs[0][a][b] = (a < k && b < k) ? A[a][b] * inv : 0.0;
       }
       __syncthreads();
+      int cur = 0;
+      for (int it = 0; it < NS_MAX_ITERS; it++) {
+        double (*X)[KM + 1] = Xs[cur];
+        double (*Y)[KM + 1] = Xs[cur ^ 1];
+        gram(X, g);
+        double dm = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+          for (int c = 0; c < 4; c++) {
+            const int a = tr + 16 * r, b = tc + 16 * c;
+            if (a < k && b < k) {
+              V[a][b] = g[r][c];
+              dm = max_nan(dm, fabs(g[r][c] - (a == b ? 1.0 : 0.0)));
+            }
+          }
+        dm = block_max4(dm, red);   // its barriers also publish V = X^T X
+        const bool last = dm <= NS_TOL;
+        double y[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+          for (int c = 0; c < 4; c++) y[r][c] = 0.0;
+#pragma unroll 2
+        for (int a = 0; a < k; a++) {
+          double xr[4], gc[4];
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            xr[r] = (tr + 16 * r < k) ? X[tr + 16 * r][a] : 0.0;
+            gc[r] = (tc + 16 * r < k) ? V[a][tc + 16 * r] : 0.0;
+          }
+#pragma unroll
+          for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) y[r][c] = fma(xr[r], gc[c], y[r][c]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+          for (int c = 0; c < 4; c++) {
+            const int i = tr + 16 * r, b = tc + 16 * c;
+            if (i < k && b < k) Y[i][b] = 1.5 * X[i][b] - 0.5 * y[r][c];
+          }
+        __syncthreads();
+        cur ^= 1;
+        if (last) {
+          polar = true;
+          break;
+        }
+      }
+      if (polar) {
+        double (*X)[KM + 1] = Xs[cur];
+        double t = 0.0;
+        for (int e = tid; e < k * k; e += 256) {
+          const int a = e / k, b = e % k;
+          t += X[a][b] * A[a][b];   // R[a][b] M[b][a]
+          Rd[e] = X[a][b];
+          Rt[e] = (T)X[a][b];
+        }
+        ssum = block_sum4(t, red);
+      }
     }
-    if (s_rot == 0) break;
+    if (!polar) {
+      // V held scratch values: back to V = I for the Jacobi SVD
+      for (int e = tid; e < KM * KM; e += 256) V[e / KM][e % KM] = (e / KM == e % KM && e / KM < k) ? 1.0 : 0.0;
+      __syncthreads();
+    }
+  }
+
+  if (!polar) {
+    // one-sided Jacobi on the columns of A (round-robin pairs; k padded to even with a zero column)
+    const int kk = k + (k & 1);
+    const int npairs = kk / 2;
+    const int tpp = 256 / 32;  // 8 threads per pair (npairs <= 32)
+    const int pair = tid / tpp, sub = tid % tpp;
+    for (int sweep = 0; sweep < 40; sweep++) {
+      if (tid == 0) s_rot = 0;
+      __syncthreads();
+      for (int step = 0; step < kk - 1; step++) {
+        if (pair < npairs) {
+          const int m = pair;
+          auto pos = [&](int x) { return x == 0 ? 0 : ((x - 1 + step) % (kk - 1)) + 1; };
+          int p = pos(m), q = pos(kk - 1 - m);
+          if (p > q) {
+            const int t = p;
+            p = q;
+            q = t;
+          }
+          double al = 0.0, be = 0.0, ga = 0.0;
+          if (q < k) {
+            for (int i = sub; i < k; i += tpp) {
+              const double x = A[p][i], y = A[q][i];
+              al += x * x;
+              be += y * y;
+              ga += x * y;
+            }
+          }
+          // reduce over the 8 lanes of the pair (consecutive lanes of one wave)
+          for (int o = tpp / 2; o > 0; o >>= 1) {
+            al += __shfl_xor(al, o, tpp);
+            be += __shfl_xor(be, o, tpp);
+            ga += __shfl_xor(ga, o, tpp);
+          }
+          if (q < k && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double t = sgn1(zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double c = 1.0 / sqrt(1.0 + t * t);
+            const double s = c * t;
+            for (int i = sub; i < k; i += tpp) {
+              const double x = A[p][i], y = A[q][i];
+              A[p][i] = c * x - s * y;
+              A[q][i] = s * x + c * y;
+              const double vx = V[p][i], vy = V[q][i];
+              V[p][i] = c * vx - s * vy;
+              V[q][i] = s * vx + c * vy;
+            }
+            if (sub == 0) s_rot = 1;
+          }
+        }
+        __syncthreads();
+      }
+      if (s_rot == 0) break;
+      __syncthreads();
+    }
+    // singular values sigma_j = |a_j|; left vectors u_j = a_j / sigma_j in place.  R = sum_j v_j u_j^T
+    // does not depend on the order of the pairs, so no sort is needed.
+    if (tid < k) {
+      double s2 = 0.0;
+      for (int i = 0; i < k; i++) s2 += A[tid][i] * A[tid][i];
+      sig[tid] = sqrt(s2);
+    }
     __syncthreads();
-  }
-  // singular values sigma_j = |a_j|; left vectors u_j = a_j / sigma_j in place.  R = sum_j v_j u_j^T
-  // does not depend on the order of the pairs, so no sort is needed.
-  if (tid < k) {
-    double s2 = 0.0;
-    for (int i = 0; i < k; i++) s2 += A[tid][i] * A[tid][i];
-    sig[tid] = sqrt(s2);
-  }
-  __syncthreads();
-  double smax = 0.0, ssum = 0.0;
-  for (int i = 0; i < k; i++) {
-    smax = fmax(smax, sig[i]);
-    ssum += sig[i];
-  }
-  int nnull = 0;
-  if (tid < k) {
-    const bool nz = smax > 0.0 && sig[tid] > 1e-12 * smax;
-    isnull[tid] = nz ? 0 : 1;
-    for (int i = 0; i < k; i++) A[tid][i] = nz ? A[tid][i] / sig[tid] : 0.0;
-  }
-  __syncthreads();
-  for (int i = 0; i < k; i++) nnull += isnull[i];
-  if (nnull > 0) {
-    complete_null_cols<KM>(A, k, isnull, tid);
-    complete_null_cols<KM>(V, k, isnull, tid);
-  }
-  __syncthreads();
-  // R = V U^T
-  for (int e = tid; e < k * k; e += 256) {
-    const int a = e / k, b = e % k;
-    double s = 0.0;
-    for (int j = 0; j < k; j++) s += V[j][a] * A[j][b];
-    Rd[e] = s;
-    Rt[e] = (T)s;
+    double smax = 0.0;
+    for (int i = 0; i < k; i++) {
+      smax = fmax(smax, sig[i]);
+      ssum += sig[i];
+    }
+    int nnull = 0;
+    if (tid < k) {
+      const bool nz = smax > 0.0 && sig[tid] > 1e-12 * smax;
+      isnull[tid] = nz ? 0 : 1;
+      for (int i = 0; i < k; i++) A[tid][i] = nz ? A[tid][i] / sig[tid] : 0.0;
+    }
+    __syncthreads();
+    for (int i = 0; i < k; i++) nnull += isnull[i];
+    if (nnull > 0) {
+      complete_null_cols<KM>(A, k, isnull, tid);
+      complete_null_cols<KM>(V, k, isnull, tid);
+    }
+    __syncthreads();
+    // R = V U^T
+    for (int e = tid; e < k * k; e += 256) {
+      const int a = e / k, b = e % k;
+      double s = 0.0;
+      for (int j = 0; j < k; j++) s += V[j][a] * A[j][b];
+      Rd[e] = s;
+      Rt[e] = (T)s;
+    }
   }
   if (tid == 0) {
     const double obj = (double)n - 2.0 * ssum;

@@ -197,6 +197,51 @@ def test_discretize_parity_planted(lib, dtype):
     assert abs(objg - objr) <= (1e-8 if dtype == "f64" else 1e-3)
 
 
+def discretize_both(lib, Qh, dtype):
+    torch = torch_mod()
+    n, k = Qh.shape
+    full = np.zeros((n, 8))
+    full[:, 1:k + 1] = Qh
+    T = torch.from_numpy(full).to(torch.float64 if dtype == "f64" else torch.float32).cuda()
+    lg, Rg, objg, itg = lib.discretize(T[:, 1:], k)
+    lr, Rr, objr, itr = oracle.discretize(T.cpu().double().numpy()[:, 1:k + 1])
+    return (lg.cpu().numpy(), Rg, objg, itg), (lr, Rr, objr, itr)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_discretize_empty_cluster(lib, dtype):
+    # rows near 6 of the 7 axes: column 6 never wins the argmax, so every step has an empty
+    # cluster (a zero row of the cluster-mean matrix), and R comes from the SVD path with the
+    # null singular vectors completed
+    rng = np.random.default_rng(5)
+    n, k = 3000, 7
+    y = rng.integers(0, k - 1, size=n)
+    Qh = np.eye(k)[y] + 0.05 * rng.standard_normal((n, k))
+    (lg, Rg, objg, itg), (lr, Rr, objr, itr) = discretize_both(lib, Qh, dtype)
+    assert np.bincount(lr, minlength=k)[k - 1] == 0
+    assert np.array_equal(lg, lr) and itg == itr
+    assert np.abs(Rg @ Rg.T - np.eye(k)).max() <= 1e-12
+    assert np.abs(Rg - Rr).max() <= (1e-10 if dtype == "f64" else 1e-5)
+    assert abs(objg - objr) <= (1e-8 if dtype == "f64" else 1e-3)
+
+
+def test_discretize_unequal_means(lib):
+    # cluster means that are not orthogonal (two at 0.85 rad, sizes 8:1, condition number 2.2):
+    # the rotation from the cluster-mean matrix must still match the oracle's V U^T
+    rng = np.random.default_rng(9)
+    n, k = 4000, 6
+    B = np.eye(k)
+    B[1] = np.cos(0.85) * B[0] + np.sin(0.85) * B[1]
+    p = np.array([8, 1, 2, 3, 4, 5], dtype=float)
+    y = rng.choice(k, size=n, p=p / p.sum())
+    Qh = B[y] + 0.005 * rng.standard_normal((n, k))
+    (lg, Rg, objg, itg), (lr, Rr, objr, itr) = discretize_both(lib, Qh, "f64")
+    assert np.bincount(lr, minlength=k).min() > 0
+    assert np.array_equal(lg, lr) and itg == itr
+    assert np.abs(Rg - Rr).max() <= 1e-10
+    assert abs(objg - objr) <= 1e-8
+
+
 @pytest.mark.parametrize("cfg", [1, 2, 4])
 def test_discretize_parity_iterated_block(lib, cfg):
     net, prm, op, ki, ks = workload(cfg)

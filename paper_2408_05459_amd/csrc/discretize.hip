@@ -241,8 +241,9 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
   // R = V U^T is the orthogonal polar factor of M^T, and trace(Omega) = trace(R M).  With every
   // cluster non-empty M is (in practice) nonsingular, and the Newton-Schulz iteration
   // X <- X (3I - X^T X) / 2 from X = M^T / s, s >= sigma_max(M) (singular values in (0, 1]),
-  // converges to that factor: the singular vectors stay, the singular values go to 1 (small ones
-  // grow by half per step, then quadratically).  One update follows the first step with
+  // converges to that factor: the singular vectors stay, the singular values go to 1.  Its steps
+  // are scaled as by Chen and Chow (a stable scaling of Newton-Schulz), which speeds up the
+  // growth of small singular values.  One plain update follows the first step with
   // max |X^T X - I| <= 1e-10.  If it does not get there (a singular M) the one-sided Jacobi SVD
   // below is used.
   double ssum = 0.0;
@@ -284,8 +285,14 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
     if (tid < k)
       for (int b = 0; b < k; b++) rs += V[tid][b];
     const double bnd = block_max4(rs, red);
+    // Gershgorin also bounds sigma_min^2 from below: min_a (2 G_aa - sum_b |G_ab|), when positive
+    const double lneg = block_max4(tid < k ? rs - 2.0 * V[tid][tid] : -INFINITY, red);
     if (bnd > 0.0) {
       const double inv = 1.0 / sqrt(bnd);
+      // ell: the assumed lower end of the singular values of X (all lie in (0, 1]); the bound
+      // above, or 1e-3 when it is smaller (a guess: a wrong one costs steps, not accuracy)
+      double ell = lneg < 0.0 ? sqrt(-lneg / bnd) : 0.0;
+      ell = fmin(fmax(ell, 1e-3), 1.0);
       for (int e = tid; e < KM * KM; e += 256) {
         const int a = e / KM, b = e % KM;
         Xs[0][a][b] = (a < k && b < k) ? A[a][b] * inv : 0.0;
@@ -309,6 +316,13 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
           }
         dm = block_max4(dm, red);   // its barriers also publish V = X^T X
         const bool last = dm <= NS_TOL;
+        // scaled step X <- (a/2) X (3I - a^2 X^T X) with a = sqrt(3 / (1 + ell + ell^2)): it maps
+        // [ell, 1] onto [ell', 1] with ell' = f(ell) = f(1), and grows small singular values
+        // by up to 3 sqrt(3) / 2 per step instead of 3/2; a -> 1 as ell -> 1.  The last step is
+        // the plain one (a = 1).
+        const double sa = last ? 1.0 : sqrt(3.0 / (1.0 + ell + ell * ell));
+        const double c1 = 1.5 * sa, c3 = 0.5 * sa * sa * sa;
+        ell = 0.5 * sa * ell * (3.0 - sa * sa * ell * ell);
         double y[4][4];
 #pragma unroll
         for (int r = 0; r < 4; r++)
@@ -332,7 +346,7 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
 #pragma unroll
           for (int c = 0; c < 4; c++) {
             const int i = tr + 16 * r, b = tc + 16 * c;
-            if (i < k && b < k) Y[i][b] = 1.5 * X[i][b] - 0.5 * y[r][c];
+            if (i < k && b < k) Y[i][b] = c1 * X[i][b] - c3 * y[r][c];
           }
         __syncthreads();
         cur ^= 1;

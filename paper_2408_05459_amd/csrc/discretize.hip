@@ -249,8 +249,14 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
   double ssum = 0.0;
   bool polar = false;
   if (!empty) {
-    // each thread owns rows tr + 16 r and columns tc + 16 s (r, s < 4) of the k x k products
+    // each thread owns rows tr + 16 r and columns tc + 16 s (r, s < 4) of the k x k products;
+    // the iterates and V are zero outside the leading k x k block, so the products read them
+    // without bounds checks (only a column index of KM or more, for KM < 64, is skipped)
     const int tr = tid >> 4, tc = tid & 15;
+    auto at = [&](double (*X)[KM + 1], int i, int j) -> double {
+      if constexpr (KM >= 64) return X[i][j];
+      else return j < KM ? X[i][j] : 0.0;
+    };
     // g = the thread's 4 x 4 block of X^T X
     auto gram = [&](double (*X)[KM + 1], double (&g)[4][4]) {
 #pragma unroll
@@ -262,8 +268,8 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
         double xa[4], xb[4];
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-          xa[r] = (tr + 16 * r < k) ? X[i][tr + 16 * r] : 0.0;
-          xb[r] = (tc + 16 * r < k) ? X[i][tc + 16 * r] : 0.0;
+          xa[r] = at(X, i, tr + 16 * r);
+          xb[r] = at(X, i, tc + 16 * r);
         }
 #pragma unroll
         for (int r = 0; r < 4; r++)
@@ -296,6 +302,7 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
       for (int e = tid; e < KM * KM; e += 256) {
         const int a = e / KM, b = e % KM;
         Xs[0][a][b] = (a < k && b < k) ? A[a][b] * inv : 0.0;
+        Xs[1][a][b] = 0.0;
       }
       __syncthreads();
       int cur = 0;
@@ -333,8 +340,8 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
           double xr[4], gc[4];
 #pragma unroll
           for (int r = 0; r < 4; r++) {
-            xr[r] = (tr + 16 * r < k) ? X[tr + 16 * r][a] : 0.0;
-            gc[r] = (tc + 16 * r < k) ? V[a][tc + 16 * r] : 0.0;
+            xr[r] = (KM >= 64 || tr + 16 * r < KM) ? X[tr + 16 * r][a] : 0.0;
+            gc[r] = at(V, a, tc + 16 * r);
           }
 #pragma unroll
           for (int r = 0; r < 4; r++)

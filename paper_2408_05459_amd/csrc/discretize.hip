@@ -143,43 +143,52 @@ __device__ __forceinline__ double sgn1(double x) { return x < 0.0 ? -1.0 : 1.0; 
 // Columns of a k x k orthogonal factor stored as B[j][i].  Each column flagged in isnull is
 // replaced, in increasing j, by the standard basis vector with the largest residual against the
 // columns already in place (all non-null ones and the null ones completed before it), projected
-// twice and normalised.  Single thread: the rank-deficient case is rare.
+// twice and normalised.  The k residual norms are computed by k threads at once (each in the
+// same order as a serial loop); the choice and the projection are made by thread 0.  All threads
+// of the workgroup call it (it has barriers); placed and n2 are k ints / doubles of LDS.
 template <int KM>
-__device__ void complete_null_cols(double (*B)[KM + 1], int k, const int* isnull, int tid) {
-  if (tid != 0) return;
-  int placed[KM];
-  for (int j = 0; j < k; j++) placed[j] = !isnull[j];
+__device__ void complete_null_cols(double (*B)[KM + 1], int k, const int* isnull, int tid, int* placed,
+                                   double* n2) {
+  if (tid < k) placed[tid] = !isnull[tid];
+  __syncthreads();
   for (int j = 0; j < k; j++) {
     if (!isnull[j]) continue;
-    int bi = 0;
-    double bn = -1.0;
-    for (int i = 0; i < k; i++) {
-      double n2 = 0.0;
+    if (tid < k) {
+      const int i = tid;
+      double s2 = 0.0;
       for (int a = 0; a < k; a++) {
         double w = (a == i) ? 1.0 : 0.0;
         for (int c = 0; c < k; c++)
           if (placed[c]) w -= B[c][a] * B[c][i];
-        n2 += w * w;
+        s2 += w * w;
       }
-      if (n2 > bn) {
-        bn = n2;
-        bi = i;
-      }
+      n2[i] = s2;
     }
-    double w[KM];
-    for (int a = 0; a < k; a++) w[a] = (a == bi) ? 1.0 : 0.0;
-    for (int pass = 0; pass < 2; pass++)
-      for (int c = 0; c < k; c++) {
-        if (!placed[c]) continue;
-        double dp = 0.0;
-        for (int a = 0; a < k; a++) dp += B[c][a] * w[a];
-        for (int a = 0; a < k; a++) w[a] -= dp * B[c][a];
-      }
-    double nn = 0.0;
-    for (int a = 0; a < k; a++) nn += w[a] * w[a];
-    nn = sqrt(nn);
-    for (int a = 0; a < k; a++) B[j][a] = w[a] / nn;
-    placed[j] = 1;
+    __syncthreads();
+    if (tid == 0) {
+      int bi = 0;
+      double bn = -1.0;
+      for (int i = 0; i < k; i++)
+        if (n2[i] > bn) {
+          bn = n2[i];
+          bi = i;
+        }
+      double w[KM];
+      for (int a = 0; a < k; a++) w[a] = (a == bi) ? 1.0 : 0.0;
+      for (int pass = 0; pass < 2; pass++)
+        for (int c = 0; c < k; c++) {
+          if (!placed[c]) continue;
+          double dp = 0.0;
+          for (int a = 0; a < k; a++) dp += B[c][a] * w[a];
+          for (int a = 0; a < k; a++) w[a] -= dp * B[c][a];
+        }
+      double nn = 0.0;
+      for (int a = 0; a < k; a++) nn += w[a] * w[a];
+      nn = sqrt(nn);
+      for (int a = 0; a < k; a++) B[j][a] = w[a] / nn;
+      placed[j] = 1;
+    }
+    __syncthreads();
   }
 }
 
@@ -219,6 +228,8 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
   __shared__ double red[4];
   __shared__ double sig[KM];
   __shared__ int isnull[KM];
+  __shared__ int placed[KM];
+  __shared__ double n2[KM];
   __shared__ int s_rot;
   const int tid = threadIdx.x;
   const int empty = __syncthreads_or(tid < k && cg[tid] == 0u);
@@ -458,8 +469,8 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
     __syncthreads();
     for (int i = 0; i < k; i++) nnull += isnull[i];
     if (nnull > 0) {
-      complete_null_cols<KM>(A, k, isnull, tid);
-      complete_null_cols<KM>(V, k, isnull, tid);
+      complete_null_cols<KM>(A, k, isnull, tid, placed, n2);
+      complete_null_cols<KM>(V, k, isnull, tid, placed, n2);
     }
     __syncthreads();
     // R = V U^T

@@ -225,6 +225,19 @@ def test_discretize_empty_cluster(lib, dtype):
     assert abs(objg - objr) <= (1e-8 if dtype == "f64" else 1e-3)
 
 
+def test_discretize_all_zero_block(lib):
+    # every row zero: all rows take label 0, the cluster-mean matrix is zero, every singular
+    # vector is completed (R = I) and obj = n at once, so the second step stops
+    torch = torch_mod()
+    n, k = 2000, 50
+    T = torch.zeros((n, 64), dtype=torch.float32, device="cuda")
+    lg, Rg, objg, itg = lib.discretize(T[:, 1:], k)
+    lr, Rr, objr, itr = oracle.discretize(np.zeros((n, k)))
+    assert np.array_equal(lg.cpu().numpy(), lr) and not lr.any()
+    assert np.array_equal(Rg, Rr) and np.array_equal(Rg, np.eye(k))
+    assert objg == objr == n and itg == itr == 2
+
+
 def test_discretize_unequal_means(lib):
     # cluster means that are not orthogonal (two at 0.85 rad, sizes 8:1, condition number 2.2):
     # the rotation from the cluster-mean matrix must still match the oracle's V U^T

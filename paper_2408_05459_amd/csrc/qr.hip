@@ -34,13 +34,27 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
     for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t r1 = (r0 + rows_per_block < n) ? r0 + rows_per_block : n;
-  for (int64_t s = r0; s < r1; s += GR_ROWS) {
-    for (int e = tid; e < GR_ROWS * 64; e += 256) {
+  // the next chunk of rows is loaded into registers while the current one is multiplied
+  constexpr int PER = GR_ROWS * 64 / 256;
+  T pre[PER];
+  auto load = [&](int64_t s) {
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const int e = tid + 256 * u;
       const int rr = e / 64, cc = e % 64;
       const int64_t row = s + rr;
-      zs[rr][cc] = (row < r1 && cc < kp) ? (double)Z[row * ld + cc] : 0.0;
+      pre[u] = (row < r1 && cc < kp) ? Z[row * ld + cc] : (T)0;
+    }
+  };
+  if (r0 < r1) load(r0);
+  for (int64_t s = r0; s < r1; s += GR_ROWS) {
+#pragma unroll
+    for (int u = 0; u < PER; u++) {
+      const int e = tid + 256 * u;
+      zs[e / 64][e % 64] = (double)pre[u];
     }
     __syncthreads();
+    if (s + GR_ROWS < r1) load(s + GR_ROWS);
     if (ty * 4 < kp && tx * 4 < kp) {
       for (int rr = 0; rr < GR_ROWS; rr++) {
         double a[4], b[4];

@@ -18,15 +18,27 @@ namespace {
 
 constexpr int GR_ROWS = 32;  // rows staged per step of the Gram kernel
 
-// partial Gram of a row range, 4x4 outputs per thread over a 64x64 grid
+// Partial Gram of a row range.  The kp x kp result is cut into 4 x 4 blocks; only the blocks on
+// or above the diagonal are computed (nt (nt + 1) / 2 of them, nt = ceil(kp / 4), one per thread,
+// packed into the first threads) and each is also written mirrored.  fma is symmetric in its
+// two factors and every block adds the rows in the same order, so the mirrored values are the
+// bits the block below the diagonal would have produced.  Entries beyond kp are written as 0.
 template <typename T>
 __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__ Z, int64_t n, int kp, int64_t ld,
                                                            int64_t rows_per_block, double* __restrict__ part,
                                                            const int* __restrict__ active) {
   if (active && *active == 0) return;
-  __shared__ double zs[GR_ROWS][64 + 1];
+  __shared__ __align__(16) double zs[GR_ROWS][64 + 2];   // 16-byte aligned rows
   const int tid = threadIdx.x;
-  const int ty = tid / 16, tx = tid % 16;
+  const int nt = (kp + 3) / 4;
+  const int npairs = nt * (nt + 1) / 2;
+  int ty = 0, tx = tid;   // the thread's block (ty <= tx) when tid < npairs
+  while (ty < nt && tx >= nt - ty) {
+    tx -= nt - ty;
+    ty++;
+  }
+  tx += ty;
+  const bool mine = tid < npairs;
   double acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; i++)
@@ -55,13 +67,14 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
     }
     __syncthreads();
     if (s + GR_ROWS < r1) load(s + GR_ROWS);
-    if (ty * 4 < kp && tx * 4 < kp) {
+    if (mine) {
       for (int rr = 0; rr < GR_ROWS; rr++) {
-        double a[4], b[4];
-#pragma unroll
-        for (int i = 0; i < 4; i++) a[i] = zs[rr][ty * 4 + i];
-#pragma unroll
-        for (int j = 0; j < 4; j++) b[j] = zs[rr][tx * 4 + j];
+        const double2 a01 = *(const double2*)&zs[rr][ty * 4];
+        const double2 a23 = *(const double2*)&zs[rr][ty * 4 + 2];
+        const double2 b01 = *(const double2*)&zs[rr][tx * 4];
+        const double2 b23 = *(const double2*)&zs[rr][tx * 4 + 2];
+        const double a[4] = {a01.x, a01.y, a23.x, a23.y};
+        const double b[4] = {b01.x, b01.y, b23.x, b23.y};
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
@@ -71,10 +84,23 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
     __syncthreads();
   }
   double* out = part + (int64_t)blockIdx.x * 64 * 64;
+  if (mine) {
 #pragma unroll
-  for (int i = 0; i < 4; i++)
+    for (int i = 0; i < 4; i++)
 #pragma unroll
-    for (int j = 0; j < 4; j++) out[(ty * 4 + i) * 64 + tx * 4 + j] = acc[i][j];
+      for (int j = 0; j < 4; j++) {
+        out[(ty * 4 + i) * 64 + tx * 4 + j] = acc[i][j];
+        out[(tx * 4 + j) * 64 + ty * 4 + i] = acc[i][j];
+      }
+  }
+  // blocks outside the nt x nt grid: zeros (thread = block (tid / 16, tid % 16) of the 16 x 16 grid)
+  const int oy = tid / 16, ox = tid % 16;
+  if (oy >= nt || ox >= nt) {
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) out[(oy * 4 + i) * 64 + ox * 4 + j] = 0.0;
+  }
 }
 
 // fixed-order sum of the per-block partials

@@ -231,14 +231,12 @@ __global__ __launch_bounds__(256) void apply_rinv_kernel(const T* __restrict__ Z
                                                          const T* __restrict__ Qprev, double* __restrict__ dq_part,
                                                          const int* __restrict__ active, int vec) {
   if (active && *active == 0) return;
-  __shared__ double Rs[KPM][KPM + 1];
   __shared__ double red[256];
   const int tid = threadIdx.x;
-  for (int e = tid; e < KPM * KPM; e += 256) {
-    const int i = e / KPM, j = e % KPM;
-    Rs[i][j] = (i < kp && j < kp) ? Rinv[i * 64 + j] : 0.0;
-  }
-  __syncthreads();
+  // R^-1 is read with addresses that are the same in every lane (scalar loads); only entries
+  // (c, j) with c <= j < kp reach a stored output
+  const double* __restrict__ Rg = Rinv;
+#define Rs(c, j) Rg[(c) * 64 + (j)]
   const int64_t r = (int64_t)blockIdx.x * 256 + tid;
   double dq = 0.0;
   // (the last row goes element by element: its vectors could run past kp to the end of ld, which
@@ -261,7 +259,7 @@ __global__ __launch_bounds__(256) void apply_rinv_kernel(const T* __restrict__ Z
         const int j = j0 + u;
         double s = 0.0;
 #pragma unroll
-        for (int c = 0; c <= j; c++) s = fma(z[c], Rs[c][j], s);
+        for (int c = 0; c <= j; c++) s = fma(z[c], Rs(c, j), s);
         qv[u] = (T)s;
       }
       if (j0 < kp) {
@@ -295,7 +293,7 @@ __global__ __launch_bounds__(256) void apply_rinv_kernel(const T* __restrict__ Z
     for (int j = 0; j < KPM; j++) {
       double s = 0.0;
 #pragma unroll
-      for (int c = 0; c <= j; c++) s = fma(z[c], Rs[c][j], s);
+      for (int c = 0; c <= j; c++) s = fma(z[c], Rs(c, j), s);
       if (j < kp) {
         const T qv = (T)s;
         if (Qprev) {
@@ -315,6 +313,7 @@ __global__ __launch_bounds__(256) void apply_rinv_kernel(const T* __restrict__ Z
     }
     if (tid == 0) dq_part[blockIdx.x] = red[0];
   }
+#undef Rs
 }
 
 __global__ void sum_partials_kernel(const double* __restrict__ part, int64_t count, double* __restrict__ out) {

@@ -40,50 +40,59 @@ def normalize_rows(X):
     return Xh, zero
 
 
-def cosine_rows(X, rows):
+def cosine_rows(X, rows, sq=None):
     """f(v_i, v_j) = cosine(X[i], X[j]) for i in ``rows`` and all j (Sec. 3.1).
 
     Computed as (x_i . x_j) / sqrt(||x_i||^2 ||x_j||^2) in FP64.  Self pairs and zero rows
-    are set to -inf (self is excluded from the K nearest neighbours, Sec. 3.1)."""
+    are set to -inf (self is excluded from the K nearest neighbours, Sec. 3.1).  ``sq``, the
+    squared row norms, may be passed in when the caller already holds them."""
     X = np.asarray(X, dtype=np.float64)
     rows = np.asarray(rows, dtype=np.int64)
-    sq = (X * X).sum(axis=1)
-    G = X[rows] @ X.T
-    den = np.sqrt(sq[rows][:, None] * sq[None, :])
+    if sq is None:
+        sq = (X * X).sum(axis=1)
+    S = X[rows] @ X.T
+    sqr = sq[rows][:, None]
     with np.errstate(divide="ignore", invalid="ignore"):
-        S = G / den
+        for c0 in range(0, S.shape[1], 1 << 16):        # column chunks only bound the temporary
+            c1 = min(S.shape[1], c0 + (1 << 16))
+            S[:, c0:c1] /= np.sqrt(sqr * sq[None, c0:c1])
     S[:, sq == 0.0] = -np.inf
     S[sq[rows] == 0.0, :] = -np.inf
     S[np.arange(rows.shape[0]), rows] = -np.inf
     return S
 
 
-def knn(X, K, rows=None, block=1024):
+def knn(X, K, rows=None, block=256):
     """N_K(v_i): the K nodes other than v_i with the largest cosine similarity (Sec. 3.1).
 
     Ties are broken by the smaller node index, i.e. candidates are ordered by the key
     (-f, j).  A zero query row, or a row with fewer than K valid candidates, is padded with
-    index -1 and similarity 0.  Returns (idx int64 [r, K], sim float64 [r, K]) sorted by key."""
+    index -1 and similarity 0.  Returns (idx int64 [r, K], sim float64 [r, K]) sorted by key.
+
+    For each query row: the K-th largest similarity s_K among its valid candidates (all of
+    them when there are fewer than K), every candidate with s >= s_K, ordered by (-s, j), the
+    first K kept."""
     X = np.asarray(X, dtype=np.float64)
     n = X.shape[0]
     rows = np.arange(n) if rows is None else np.asarray(rows, dtype=np.int64)
+    sq = (X * X).sum(axis=1)
     out_i = np.full((rows.shape[0], K), -1, dtype=np.int64)
     out_s = np.zeros((rows.shape[0], K), dtype=np.float64)
     for b0 in range(0, rows.shape[0], block):
         rb = rows[b0:b0 + block]
-        S = cosine_rows(X, rb)
-        for t in range(rb.shape[0]):
-            s = S[t]
-            valid = np.nonzero(s > -np.inf)[0]
-            if valid.shape[0] == 0:
-                continue
-            kk = min(K, valid.shape[0])
-            sv = s[valid]
-            kth = np.partition(sv, sv.shape[0] - kk)[sv.shape[0] - kk]
-            cand = valid[sv >= kth]
-            order = np.lexsort((cand, -s[cand]))[:kk]
-            out_i[b0 + t, :kk] = cand[order]
-            out_s[b0 + t, :kk] = s[cand[order]]
+        S = cosine_rows(X, rb, sq)
+        kk = np.minimum(K, (S > -np.inf).sum(axis=1))
+        # the K-th largest value of each row (-inf entries sort below every valid one)
+        kth = np.partition(S, n - K, axis=1)[:, n - K]
+        kth[kk < K] = -np.inf
+        r, c = np.nonzero((S >= kth[:, None]) & (S > -np.inf))
+        s = S[r, c]
+        order = np.lexsort((c, -s, r))
+        r, c, s = r[order], c[order], s[order]
+        pos = np.arange(r.shape[0]) - np.searchsorted(r, r)
+        keep = pos < kk[r]
+        out_i[b0 + r[keep], pos[keep]] = c[keep]
+        out_s[b0 + r[keep], pos[keep]] = s[keep]
     return out_i, out_s
 
 

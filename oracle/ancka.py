@@ -426,13 +426,19 @@ def mhc(op: Operator, labels, k, alpha, gamma):
 
     Note: with gamma finite the rows of S sum to 1 - (1-alpha)^(gamma+1), so this value
     exceeds Phi of Eq. (mh-cond) by exactly (1-alpha)^(gamma+1); the algorithm's value is
-    the one the method compares."""
+    the one the method compares.
+
+    The trace is summed node by node, sum_i Yh[i, c(i)] F[i, c(i)], so that phi is a function of
+    the partition alone: renaming the clusters permutes the columns of F, and each column is
+    computed by the same arithmetic, so the summands and their order do not change."""
+    labels = np.asarray(labels, dtype=np.int64)
     Yh = normalized_bcm(labels, k)
     F0 = alpha * Yh
     F = F0
     for _ in range(gamma):
         F = (1.0 - alpha) * apply_P(op, F) + F0
-    return 1.0 - float(np.sum(Yh * F)) / k
+    rows = np.arange(labels.shape[0])
+    return 1.0 - float(np.sum(Yh[rows, labels] * F[rows, labels])) / k
 
 
 # --------------------------------------------------------------------------------------

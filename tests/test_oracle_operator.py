@@ -233,3 +233,21 @@ def test_mhc_lemma1_upper_bound():
         labels = rng.permutation(np.arange(n) % k)
         psi = 1.0 - oracle.mhc(op, labels, k, alpha, gamma)
         assert psi <= psi_sigma + 1e-12
+
+
+def test_mhc_is_a_function_of_the_partition():
+    # renaming the clusters (Alg. 2 scores a partition) leaves phi bit-identical, also when a
+    # cluster is empty; checked on a generated workload (k = 50) where the order of the sum
+    # would otherwise show in the last bits
+    from paper_2408_05459_amd import synth
+    net, prm = synth.make_config(4, scale=0.002)
+    _, zero = oracle.normalize_rows(net.X)
+    ki, ks = oracle.knn(net.X, prm.K)
+    op = oracle.build_operator(net.kind, net.n, net.ptrs, net.idxs, net.m, zero, ki, ks, prm.beta)
+    rng = np.random.default_rng(3)
+    y = rng.integers(0, net.k, size=net.n)
+    for labels in (y, np.where(y == 4, 5, y)):
+        phi = oracle.mhc(op, labels, net.k, prm.alpha, prm.gamma)
+        for _ in range(6):
+            perm = rng.permutation(net.k)
+            assert oracle.mhc(op, perm[labels], net.k, prm.alpha, prm.gamma) == phi

@@ -19,8 +19,8 @@ Parity status per function:
   orth_iter                                    pinned (eigh of the symmetric similar matrix)
   discretize                                   pinned (planted rotation, polar factor)
   mhc                                          pinned (escape-probability definition, offset identity)
-  cluster                                      parity unpinned beyond its steps (heuristic path);
-                                               sanity-pinned on strongly planted inputs
+  cluster                                      pinned (scripted conductance and step norms fix the
+                                               stop, its reason and the returned labels; planted inputs)
   mlp_*                                        pinned (central finite differences)
 """
 from .ancka import *  # noqa: F401,F403

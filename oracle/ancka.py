@@ -1,13 +1,15 @@
 """FP64 oracle of the clustering path (TEST INFRASTRUCTURE ONLY; see package docstring).
 
 Plain numpy / scipy.sparse in float64.  Library primitives used as single steps:
-matrix products (dense and sparse), numpy.linalg.qr (Householder QR) and
+matrix products (dense and sparse), numpy.linalg.qr (Householder QR),
 numpy.linalg.svd.  No blocking, fusion or reordering beyond what the paper's
 equations state.
 """
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import List, Optional
 
@@ -40,8 +42,9 @@ def normalize_rows(X):
     return Xh, zero
 
 
-def cosine_rows(X, rows, sq=None):
-    """f(v_i, v_j) = cosine(X[i], X[j]) for i in ``rows`` and all j (Sec. 3.1).
+def cosine_rows(X, rows, sq=None, cols=None):
+    """f(v_i, v_j) = cosine(X[i], X[j]) for i in ``rows`` and j in ``cols`` (a range c0..c1-1,
+    default all nodes) (Sec. 3.1).
 
     Computed as (x_i . x_j) / sqrt(||x_i||^2 ||x_j||^2) in FP64.  Self pairs and zero rows
     are set to -inf (self is excluded from the K nearest neighbours, Sec. 3.1).  ``sq``, the
@@ -50,49 +53,65 @@ def cosine_rows(X, rows, sq=None):
     rows = np.asarray(rows, dtype=np.int64)
     if sq is None:
         sq = (X * X).sum(axis=1)
-    S = X[rows] @ X.T
-    sqr = sq[rows][:, None]
+    c0, c1 = (0, X.shape[0]) if cols is None else cols
+    S = X[rows] @ X[c0:c1].T
     with np.errstate(divide="ignore", invalid="ignore"):
-        for c0 in range(0, S.shape[1], 1 << 16):        # column chunks only bound the temporary
-            c1 = min(S.shape[1], c0 + (1 << 16))
-            S[:, c0:c1] /= np.sqrt(sqr * sq[None, c0:c1])
-    S[:, sq == 0.0] = -np.inf
+        S /= np.sqrt(sq[rows][:, None] * sq[None, c0:c1])
+    S[:, sq[c0:c1] == 0.0] = -np.inf
     S[sq[rows] == 0.0, :] = -np.inf
-    S[np.arange(rows.shape[0]), rows] = -np.inf
+    own = (rows >= c0) & (rows < c1)
+    S[np.nonzero(own)[0], rows[own] - c0] = -np.inf
     return S
 
 
-def knn(X, K, rows=None, block=256):
+def knn(X, K, rows=None, block=512, width=16384, threads=None):
     """N_K(v_i): the K nodes other than v_i with the largest cosine similarity (Sec. 3.1).
 
     Ties are broken by the smaller node index, i.e. candidates are ordered by the key
     (-f, j).  A zero query row, or a row with fewer than K valid candidates, is padded with
     index -1 and similarity 0.  Returns (idx int64 [r, K], sim float64 [r, K]) sorted by key.
 
-    For each query row: the K-th largest similarity s_K among its valid candidates (all of
-    them when there are fewer than K), every candidate with s >= s_K, ordered by (-s, j), the
-    first K kept."""
+    For each query row: t0, the K-th largest valid similarity among the first ``width``
+    nodes (-inf when there are fewer than K of them).  The row holds at least K valid
+    similarities >= t0, so its K-th largest is >= t0 and every member of its top K by the
+    key is among the valid entries >= t0.  Those entries are collected slice by slice of
+    ``width`` columns (on ``threads`` threads, each with single-threaded BLAS), ordered by
+    (-f, j), and the first K kept (all of them when there are fewer than K)."""
+    from threadpoolctl import threadpool_limits
+
     X = np.asarray(X, dtype=np.float64)
     n = X.shape[0]
     rows = np.arange(n) if rows is None else np.asarray(rows, dtype=np.int64)
     sq = (X * X).sum(axis=1)
     out_i = np.full((rows.shape[0], K), -1, dtype=np.int64)
     out_s = np.zeros((rows.shape[0], K), dtype=np.float64)
-    for b0 in range(0, rows.shape[0], block):
-        rb = rows[b0:b0 + block]
-        S = cosine_rows(X, rb, sq)
-        kk = np.minimum(K, (S > -np.inf).sum(axis=1))
-        # the K-th largest value of each row (-inf entries sort below every valid one)
-        kth = np.partition(S, n - K, axis=1)[:, n - K]
-        kth[kk < K] = -np.inf
-        r, c = np.nonzero((S >= kth[:, None]) & (S > -np.inf))
-        s = S[r, c]
-        order = np.lexsort((c, -s, r))
-        r, c, s = r[order], c[order], s[order]
-        pos = np.arange(r.shape[0]) - np.searchsorted(r, r)
-        keep = pos < kk[r]
-        out_i[b0 + r[keep], pos[keep]] = c[keep]
-        out_s[b0 + r[keep], pos[keep]] = s[keep]
+    w0 = min(n, width)
+    slices = [(c0, min(n, c0 + width)) for c0 in range(0, n, width)]
+    with threadpool_limits(limits=1, user_api="blas"), \
+            ThreadPoolExecutor(max_workers=threads or os.cpu_count() or 1) as ex:
+        for b0 in range(0, rows.shape[0], block):
+            rb = rows[b0:b0 + block]
+            S0 = cosine_rows(X, rb, sq, (0, w0))
+            t0 = np.full(rb.shape[0], -np.inf)
+            if w0 >= K:
+                kth = np.partition(S0, w0 - K, axis=1)[:, w0 - K]   # -inf sorts lowest
+                t0 = np.where(kth > -np.inf, kth, -np.inf)
+
+            def survivors(c):
+                Sc = cosine_rows(X, rb, sq, c)
+                r, j = np.nonzero((Sc >= t0[:, None]) & (Sc > -np.inf))
+                return r, j + c[0], Sc[r, j]
+
+            parts = list(ex.map(survivors, slices))
+            r = np.concatenate([p[0] for p in parts])
+            j = np.concatenate([p[1] for p in parts])
+            s = np.concatenate([p[2] for p in parts])
+            order = np.lexsort((j, -s, r))
+            r, j, s = r[order], j[order], s[order]
+            pos = np.arange(r.shape[0]) - np.searchsorted(r, r)
+            keep = pos < K
+            out_i[b0 + r[keep], pos[keep]] = j[keep]
+            out_s[b0 + r[keep], pos[keep]] = s[keep]
     return out_i, out_s
 
 

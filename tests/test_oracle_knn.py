@@ -139,3 +139,25 @@ def test_knn_adjacency_symmetric_nonnegative():
                 continue
             mutual = i in idx[j]
             assert math.isclose(A[i, j], (2 if mutual else 1) * sim[i, t], rel_tol=1e-15)
+
+
+@pytest.mark.parametrize("width", [3, 16, 41])
+def test_knn_sliced_threshold_matches_brute_force(width):
+    """The lower bound t0 taken from the first ``width`` columns never drops a member of the
+    top K: narrow slices (one narrower than K, so t0 = -inf) give the brute-force lists,
+    including exact ties of duplicated binary rows."""
+    rng = np.random.default_rng(6)
+    X = (rng.random((90, 10)) < 0.35).astype(np.float64)
+    X[30] = X[2]
+    X[61] = X[2]
+    X[7] = 0.0
+    K = 5
+    idx, sim = oracle.knn(X, K, width=width, block=17)
+    ref = brute_knn(X.tolist(), K)
+    for i in range(90):
+        if i == 7:
+            assert (idx[i] == -1).all()
+            continue
+        assert idx[i].tolist() == ref[i], i
+    full_i, full_s = oracle.knn(X, K)
+    assert np.array_equal(idx, full_i) and np.array_equal(sim, full_s)

@@ -218,8 +218,10 @@ ancka_status ancka_orth_iter(ancka_ctx* ctx, const ancka_op* op, void* Q, int64_
  * ties), Y~ = Y with columns divided by their sums, U Omega V^T = SVD(Y~^T Q~), R = V U^T,
  * obj = n - 2 trace(Omega); stops when |obj - obj_prev| <= 1e-12 max(1, |obj|) or after
  * max_iter steps.  labels: int32 n (device); R: host k x k row-major, nullable; obj, iters: host,
- * nullable.  Synchronises the stream.
- * Errors: INVALID_ARG unless 1 <= k <= 64, n >= 1, max_iter >= 1. */
+ * nullable.  Synchronises the stream.  The cluster sums are exact fixed-point integers (scale
+ * 2^40, or 2^(62 - ceil(log2 n)) when n > 2^22), so they do not depend on the order of rows.
+ * Errors: INVALID_ARG unless 1 <= k <= 64, 1 <= n < 2^31, ldq >= k, max_iter >= 1 and qdtype is
+ * F32 or F64. */
 ancka_status ancka_discretize(ancka_ctx* ctx, const void* Q, int32_t qdtype, int64_t n, int32_t k,
                               int64_t ldq, int32_t max_iter, int32_t* labels, double* R, double* obj,
                               int32_t* iters);

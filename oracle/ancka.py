@@ -76,13 +76,16 @@ def knn(X, K, rows=None, block=512, width=16384, threads=None):
     similarities >= t0, so its K-th largest is >= t0 and every member of its top K by the
     key is among the valid entries >= t0.  Those entries are collected slice by slice of
     ``width`` columns (on ``threads`` threads, each with single-threaded BLAS), ordered by
-    (-f, j), and the first K kept (all of them when there are fewer than K)."""
+    (-f, j), and the first K kept (all of them when there are fewer than K).  Within a slice
+    the cosine formula is evaluated only where the dot product passes a bound that no entry
+    >= t0 can fail."""
     from threadpoolctl import threadpool_limits
 
     X = np.asarray(X, dtype=np.float64)
     n = X.shape[0]
     rows = np.arange(n) if rows is None else np.asarray(rows, dtype=np.int64)
     sq = (X * X).sum(axis=1)
+    nrm = np.sqrt(sq)
     out_i = np.full((rows.shape[0], K), -1, dtype=np.int64)
     out_s = np.zeros((rows.shape[0], K), dtype=np.float64)
     w0 = min(n, width)
@@ -98,9 +101,19 @@ def knn(X, K, rows=None, block=512, width=16384, threads=None):
                 t0 = np.where(kth > -np.inf, kth, -np.inf)
 
             def survivors(c):
-                Sc = cosine_rows(X, rb, sq, c)
-                r, j = np.nonzero((Sc >= t0[:, None]) & (Sc > -np.inf))
-                return r, j + c[0], Sc[r, j]
+                # entries whose cosine can reach t0: dot >= (t0 - 1e-12) |x_i| |x_j| (the
+                # margin exceeds the rounding of both sides by far); their cosines are then
+                # computed by the formula above, and self pairs and zero rows dropped
+                c0, c1 = c
+                # (t0 = -inf against a zero norm gives NaN, which passes nothing: zero rows
+                # are never candidates)
+                D = X[rb] @ X[c0:c1].T
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    r, j = np.nonzero(D >= ((t0 - 1e-12) * nrm[rb])[:, None] * nrm[None, c0:c1])
+                    jj = j + c0
+                    f = D[r, j] / np.sqrt(sq[rb[r]] * sq[jj])
+                ok = (sq[rb[r]] > 0.0) & (sq[jj] > 0.0) & (rb[r] != jj) & (f >= t0[r])
+                return r[ok], jj[ok], f[ok]
 
             parts = list(ex.map(survivors, slices))
             r = np.concatenate([p[0] for p in parts])

@@ -3,8 +3,10 @@
 // Per step two kernels run:
 //  disc_pass  one thread per row: q~ = q / |q| (zero rows stay zero), t = q~ R, label = first
 //             argmax of t; the row is added to its cluster's sum S[label] and count.  The sums
-//             are kept in 2^-40 fixed point (|q~_c| <= 1) with 64-bit integer atomics, so
-//             they are exact and independent of the order in which rows arrive.
+//             are kept in 2^-s fixed point (|q~_c| <= 1) with 64-bit integer atomics, so
+//             they are exact and independent of the order in which rows arrive; s = 40, or
+//             62 - ceil(log2 n) when n > 2^22, so that n rows of magnitude <= 2^s cannot
+//             reach 2^63.
 //  disc_svd   one workgroup: M = S / count (rows of M are cluster means of q~, i.e. Y~^T Q~ with
 //             the column sums of Y as divisors); R = V U^T and trace(Omega) of M = U Omega V^T,
 //             in FP64; obj = n - 2 trace(Omega); sets a device flag when |obj - obj_prev| <=
@@ -23,7 +25,13 @@
 
 namespace {
 
-constexpr double FIX_SCALE = 1099511627776.0;  // 2^40
+// 2^s of the fixed-point cluster sums: n (2^s + 1) < 2^63 for every n < 2^31.
+inline double fix_scale(int64_t n) {
+  int b = 0;
+  while (b < 62 && ((int64_t)1 << b) < n) b++;   // 2^b >= n
+  const int s = b > 22 ? 62 - b : 40;
+  return std::ldexp(1.0, s);
+}
 
 struct DiscState {
   int done;
@@ -40,7 +48,7 @@ __global__ __launch_bounds__(256) void disc_pass_kernel(const T* __restrict__ Q,
                                                         const T* __restrict__ R, int32_t* __restrict__ labels,
                                                         unsigned long long* __restrict__ Sg,
                                                         unsigned int* __restrict__ cg,
-                                                        const DiscState* __restrict__ st) {
+                                                        const DiscState* __restrict__ st, double fscale) {
   if (st->done) return;
   __shared__ __align__(16) T Rs[KM][KM];   // Rs[j][c] = R[c][j] (zero outside k x k)
   __shared__ unsigned long long Ss[KM * KM];
@@ -125,7 +133,7 @@ __global__ __launch_bounds__(256) void disc_pass_kernel(const T* __restrict__ Q,
 #pragma unroll
     for (int c = 0; c < KM; c++)
       if (c < k) {
-        const long long f = llrint((double)q[c] * FIX_SCALE);
+        const long long f = llrint((double)q[c] * fscale);
         if (f != 0) atomicAdd(&Ss[best * KM + c], (unsigned long long)f);
       }
   }
@@ -220,7 +228,7 @@ constexpr double NS_TOL = 1e-10;   // max |X^T X - I| before the last update
 template <typename T, int KM>
 __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __restrict__ Sg, unsigned int* __restrict__ cg,
                                                        int k, int64_t n, double* __restrict__ Rd, T* __restrict__ Rt,
-                                                       DiscState* __restrict__ st) {
+                                                       DiscState* __restrict__ st, double fscale) {
   if (st->done) return;
   __shared__ double A[KM][KM + 1];   // A[j][i] = column j of M (then of M V)
   __shared__ double V[KM][KM + 1];   // V[j][i] = column j of V; X^T X in the Newton-Schulz path
@@ -233,14 +241,14 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
   __shared__ int s_rot;
   const int tid = threadIdx.x;
   const int empty = __syncthreads_or(tid < k && cg[tid] == 0u);
-  // M[c][j] = S[c][j] 2^-40 / count[c]; then clear S and counts for the next step
+  // M[c][j] = S[c][j] / (2^s count[c]); then clear S and counts for the next step
   for (int e = tid; e < KM * KM; e += 256) {
     const int c = e / KM, j = e % KM;
     double v = 0.0;
     if (c < k && j < k) {
       const unsigned int cnt = cg[c];
       const long long s = (long long)Sg[c * k + j];
-      v = cnt ? ((double)s / FIX_SCALE) / (double)cnt : 0.0;
+      v = cnt ? ((double)s / fscale) / (double)cnt : 0.0;
     }
     A[j][c] = v;
     V[j][c] = (c == j && c < k) ? 1.0 : 0.0;
@@ -510,19 +518,39 @@ __global__ void disc_init_kernel(int k, double* __restrict__ Rd, T* __restrict__
   }
 }
 
+// Device state of one Discretize call: R (FP64 and in the block's type), the fixed-point
+// cluster sums, the counts and the loop state.  Every entry point passes memory of at least
+// DISC_STATE_BYTES, 256-byte aligned.
+struct DiscBufs {
+  double* Rd;
+  void* Rt;
+  unsigned long long* Sg;
+  unsigned int* cg;
+  DiscState* st;
+};
+constexpr size_t DISC_R_BYTES = 64 * 64 * sizeof(double);
+constexpr size_t DISC_STATE_BYTES = 3 * DISC_R_BYTES + 256 + 256;
+
+DiscBufs disc_bufs_at(void* base) {
+  char* b = (char*)base;
+  DiscBufs d;
+  d.Rd = (double*)b;
+  d.Rt = (void*)(b + DISC_R_BYTES);
+  d.Sg = (unsigned long long*)(b + 2 * DISC_R_BYTES);
+  d.cg = (unsigned int*)(b + 3 * DISC_R_BYTES);
+  d.st = (DiscState*)(b + 3 * DISC_R_BYTES + 256);
+  return d;
+}
+
 template <typename T, int KM>
 ancka_status disc_launch(ancka_ctx* ctx, const T* Q, int64_t n, int k, int64_t ldq, int max_iter, int32_t* labels,
-                         double* Rh, double* obj, int32_t* iters) {
-  double* Rd = nullptr;
-  T* Rt = nullptr;
-  unsigned long long* Sg = nullptr;
-  unsigned int* cg = nullptr;
-  DiscState* st = nullptr;
-  ST_TRY(ws_get_t(ctx, "disc_Rd", 64 * 64, &Rd));
-  ST_TRY(ws_get_t(ctx, "disc_Rt", 64 * 64, &Rt));
-  ST_TRY(ws_get_t(ctx, "disc_S", 64 * 64, &Sg));
-  ST_TRY(ws_get_t(ctx, "disc_c", 64, &cg));
-  ST_TRY(ws_get_t(ctx, "disc_st", 1, &st));
+                         double* Rh, double* obj, int32_t* iters, const DiscBufs& b) {
+  double* Rd = b.Rd;
+  T* Rt = (T*)b.Rt;
+  unsigned long long* Sg = b.Sg;
+  unsigned int* cg = b.cg;
+  DiscState* st = b.st;
+  const double fscale = fix_scale(n);
   disc_init_kernel<T><<<16, 256, 0, ctx->stream>>>(k, Rd, Rt, st, Sg, cg);
   LAUNCH_CHECK(ctx);
   const unsigned grid = (unsigned)cdiv(n, 256);
@@ -534,11 +562,14 @@ ancka_status disc_launch(ancka_ctx* ctx, const T* Q, int64_t n, int k, int64_t l
       if (((uintptr_t)(Q - o) % 16) == 0 && o + k <= ldq) voff = o;
   DiscState hs{0, 0, 0.0, 0.0};
   for (int it = 0; it < max_iter; it++) {
-    if (voff == 0) disc_pass_kernel<T, KM, 0><<<grid, 256, 0, ctx->stream>>>(Q, n, k, ldq, Rt, labels, Sg, cg, st);
-    else if (voff == 1) disc_pass_kernel<T, KM, 1><<<grid, 256, 0, ctx->stream>>>(Q, n, k, ldq, Rt, labels, Sg, cg, st);
-    else disc_pass_kernel<T, KM, -1><<<grid, 256, 0, ctx->stream>>>(Q, n, k, ldq, Rt, labels, Sg, cg, st);
+    if (voff == 0)
+      disc_pass_kernel<T, KM, 0><<<grid, 256, 0, ctx->stream>>>(Q, n, k, ldq, Rt, labels, Sg, cg, st, fscale);
+    else if (voff == 1)
+      disc_pass_kernel<T, KM, 1><<<grid, 256, 0, ctx->stream>>>(Q, n, k, ldq, Rt, labels, Sg, cg, st, fscale);
+    else
+      disc_pass_kernel<T, KM, -1><<<grid, 256, 0, ctx->stream>>>(Q, n, k, ldq, Rt, labels, Sg, cg, st, fscale);
     LAUNCH_CHECK(ctx);
-    disc_svd_kernel<T, KM><<<1, 256, 0, ctx->stream>>>(Sg, cg, k, n, Rd, Rt, st);
+    disc_svd_kernel<T, KM><<<1, 256, 0, ctx->stream>>>(Sg, cg, k, n, Rd, Rt, st, fscale);
     LAUNCH_CHECK(ctx);
     if ((it % 4) == 3 || it == max_iter - 1) {
       HIP_TRY(ctx, hipMemcpyAsync(&hs, st, sizeof(DiscState), hipMemcpyDeviceToHost, ctx->stream));
@@ -547,10 +578,8 @@ ancka_status disc_launch(ancka_ctx* ctx, const T* Q, int64_t n, int k, int64_t l
     }
   }
   if (Rh) {
-    std::vector<double> h(k * k);
-    HIP_TRY(ctx, hipMemcpyAsync(h.data(), Rd, sizeof(double) * k * k, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(Rh, Rd, sizeof(double) * k * k, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    for (int e = 0; e < k * k; e++) Rh[e] = h[e];
   }
   if (obj) *obj = hs.obj;
   if (iters) *iters = hs.iters;
@@ -559,29 +588,44 @@ ancka_status disc_launch(ancka_ctx* ctx, const T* Q, int64_t n, int k, int64_t l
 
 template <typename T>
 ancka_status disc_typed(ancka_ctx* ctx, const T* Q, int64_t n, int k, int64_t ldq, int max_iter, int32_t* labels,
-                        double* Rh, double* obj, int32_t* iters) {
-  if (k <= 8) return disc_launch<T, 8>(ctx, Q, n, k, ldq, max_iter, labels, Rh, obj, iters);
-  if (k <= 16) return disc_launch<T, 16>(ctx, Q, n, k, ldq, max_iter, labels, Rh, obj, iters);
-  if (k <= 32) return disc_launch<T, 32>(ctx, Q, n, k, ldq, max_iter, labels, Rh, obj, iters);
-  return disc_launch<T, 64>(ctx, Q, n, k, ldq, max_iter, labels, Rh, obj, iters);
+                        double* Rh, double* obj, int32_t* iters, const DiscBufs& b) {
+  if (k <= 8) return disc_launch<T, 8>(ctx, Q, n, k, ldq, max_iter, labels, Rh, obj, iters, b);
+  if (k <= 16) return disc_launch<T, 16>(ctx, Q, n, k, ldq, max_iter, labels, Rh, obj, iters, b);
+  if (k <= 32) return disc_launch<T, 32>(ctx, Q, n, k, ldq, max_iter, labels, Rh, obj, iters, b);
+  return disc_launch<T, 64>(ctx, Q, n, k, ldq, max_iter, labels, Rh, obj, iters, b);
+}
+
+ancka_status disc_dispatch(ancka_ctx* ctx, const void* Q, int qdtype, int64_t n, int k, int64_t ldq, int max_iter,
+                           int32_t* labels, double* R, double* obj, int32_t* iters, const DiscBufs& b) {
+  if (qdtype == ANCKA_F64)
+    return disc_typed<double>(ctx, (const double*)Q, n, k, ldq, max_iter, labels, R, obj, iters, b);
+  return disc_typed<float>(ctx, (const float*)Q, n, k, ldq, max_iter, labels, R, obj, iters, b);
+}
+
+ancka_status disc_check_args(ancka_ctx* ctx, const char* fn, const void* Q, int32_t qdtype, int64_t n, int32_t k,
+                             int64_t ldq, int32_t max_iter, const int32_t* labels) {
+  if (!ctx) return ANCKA_ERR_INVALID_ARG;
+  if (!Q || !labels || k < 1 || k > 64 || n < 1 || n >= ((int64_t)1 << 31) || ldq < k || max_iter < 1 ||
+      (qdtype != ANCKA_F32 && qdtype != ANCKA_F64))
+    return set_err(ctx, ANCKA_ERR_INVALID_ARG, "%s: n=%lld k=%d ldq=%lld max_iter=%d qdtype=%d (need 1 <= k <= 64, "
+                   "1 <= n < 2^31, ldq >= k, max_iter >= 1, F32 or F64)", fn, (long long)n, k, (long long)ldq,
+                   max_iter, qdtype);
+  return ANCKA_OK;
 }
 
 }  // namespace
 
 ancka_status discretize_internal(ancka_ctx* ctx, const void* Q, int qdtype, int64_t n, int k, int64_t ldq,
                                  int max_iter, int32_t* labels, double* R, double* obj, int32_t* iters) {
-  if (qdtype == ANCKA_F64)
-    return disc_typed<double>(ctx, (const double*)Q, n, k, ldq, max_iter, labels, R, obj, iters);
-  return disc_typed<float>(ctx, (const float*)Q, n, k, ldq, max_iter, labels, R, obj, iters);
+  void* base = nullptr;
+  ST_TRY(ws_get(ctx, "disc_state", DISC_STATE_BYTES, &base));
+  return disc_dispatch(ctx, Q, qdtype, n, k, ldq, max_iter, labels, R, obj, iters, disc_bufs_at(base));
 }
 
 extern "C" ancka_status ancka_discretize(ancka_ctx* ctx, const void* Q, int32_t qdtype, int64_t n, int32_t k,
                                          int64_t ldq, int32_t max_iter, int32_t* labels, double* R, double* obj,
                                          int32_t* iters) {
-  if (!ctx || !Q || !labels) return ANCKA_ERR_INVALID_ARG;
-  if (k < 1 || k > 64 || n < 1 || ldq < k || max_iter < 1 || (qdtype != ANCKA_F32 && qdtype != ANCKA_F64))
-    return set_err(ctx, ANCKA_ERR_INVALID_ARG, "ancka_discretize: n=%lld k=%d ldq=%lld max_iter=%d", (long long)n, k,
-                   (long long)ldq, max_iter);
+  ST_TRY(disc_check_args(ctx, "ancka_discretize", Q, qdtype, n, k, ldq, max_iter, labels));
   if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, ANCKA_ERR_HIP, "hipSetDevice");
   return discretize_internal(ctx, Q, qdtype, n, k, ldq, max_iter, labels, R, obj, iters);
 }

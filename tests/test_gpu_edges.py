@@ -157,3 +157,164 @@ def test_full_size_benchmark_graph_sampled(lib):
     ones = torch.ones((net.n, 52), dtype=torch.float32, device="cuda")
     P1 = op.apply(ones)
     assert float((P1 - 1.0).abs().max()) <= 1e-5
+
+
+def test_discretize_cluster_beyond_2_pow_23_rows(lib):
+    """One cluster of 2^23 + 4096 rows equal to (1, 0): the fixed-point cluster sum would be
+    2^63 + 2^52 at the scale 2^40; the scale chosen from n keeps it exact, so the cluster mean
+    is (1, 0) and the objective is the oracle's."""
+    import torch
+    import oracle
+    n, k = (1 << 23) + 4096, 2
+    T = torch.zeros((n, k), dtype=torch.float32, device="cuda")
+    T[:, 0] = 1.0
+    lg, Rg, objg, itg = lib.discretize(T, k)
+    lr, Rr, objr, itr = oracle.discretize(np.tile([1.0, 0.0], (n, 1)))
+    assert not lg.any().item() and not lr.any()
+    assert np.abs(Rg - Rr).max() <= 1e-12 and itg == itr
+    assert abs(objg - objr) <= 1e-6 and abs(objr - (n - 2.0)) <= 1e-6
+
+
+def _messy_csr(n, ptr, idx, rng):
+    """The same undirected graph given as a messy directed CSR: of each edge pair (i, j),
+    (j, i) a random one of the two directions is dropped half of the time, 3% of the entries
+    are repeated, self loops are added at 2% of the nodes, and every row's columns are
+    shuffled.  The method reads it as the original simple graph (Sec. 6.1: reverse edges
+    added; A is binary; self loops dropped)."""
+    rows = np.repeat(np.arange(n), np.diff(ptr))
+    cols = np.asarray(idx, dtype=np.int64)
+    lo, hi = np.minimum(rows, cols), np.maximum(rows, cols)
+    drop = rng.random(rows.shape[0]) < 0.5
+    keep_dir = ((lo * 7919 + hi) % 2 == 0)            # the direction kept, one per pair
+    keep = ~drop | ((rows < cols) == keep_dir)
+    r, c = rows[keep], cols[keep]
+    dup = rng.random(r.shape[0]) < 0.03
+    loops = rng.choice(n, size=max(1, n // 50), replace=False)
+    r = np.concatenate([r, r[dup], loops])
+    c = np.concatenate([c, c[dup], loops])
+    order = np.lexsort((rng.random(r.shape[0]), r))
+    r, c = r[order], c[order]
+    p = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(p, r + 1, 1)
+    return np.cumsum(p), c.astype(np.int32)
+
+
+@pytest.mark.parametrize("cfg,scale", [(1, 0.5), (3, 0.006), (4, 0.002)])
+def test_operator_parity_messy_topology(lib, cfg, scale):
+    """Directed edges, duplicate entries, self loops and unsorted rows (graph and multiplex),
+    repeated hyperedge members (hypergraph): the GPU operator equals the oracle's, which reads
+    them as Sec. 6.1 and Sec. 2 define the simple network."""
+    import dataclasses
+    torch = torch_mod()
+    net, prm = synth.make_config(cfg, scale=scale)
+    rng = np.random.default_rng(100 + cfg)
+    if net.kind == synth.HYPERGRAPH:
+        ptr, idx = net.ptrs[0], net.idxs[0]
+        sizes = np.diff(ptr)
+        members = np.split(idx, ptr[1:-1])
+        new = []
+        for e in members:
+            extra = e[rng.random(e.shape[0]) < 0.2]
+            new.append(rng.permutation(np.concatenate([e, extra, e[:1]])))
+        p2 = np.zeros(len(new) + 1, dtype=np.int64)
+        p2[1:] = np.cumsum([len(e) for e in new])
+        messy = dataclasses.replace(net, ptrs=[p2], idxs=[np.concatenate(new).astype(np.int32)])
+        assert (np.diff(p2) > sizes).all()
+    else:
+        ps, ix = [], []
+        for p, i in zip(net.ptrs, net.idxs):
+            p2, i2 = _messy_csr(net.n, p, i, rng)
+            ps.append(p2)
+            ix.append(i2)
+        messy = dataclasses.replace(net, ptrs=ps, idxs=ix)
+    op_clean, ki, ks = oracle_operator(net, prm.K, prm.beta)
+    op_messy, _, _ = oracle_operator(messy, prm.K, prm.beta, knn=(ki, ks))
+    # the oracle reads both as the same network
+    assert np.array_equal(op_clean.delta, op_messy.delta) and np.array_equal(op_clean.beta, op_messy.beta)
+    s, keep = lib.network(messy)
+    gop = lib.build_operator(s, torch.from_numpy(ki.astype(np.int32)).cuda(),
+                             torch.from_numpy(ks.astype(np.float64 if prm.q_dtype == "f64" else np.float32)).cuda(),
+                             prm.K, prm.beta, prm.q_dtype)
+    info = gop.info()
+    assert np.array_equal(info["delta"], op_messy.delta.astype(np.int64))
+    assert np.array_equal(info["beta"], op_messy.beta)
+    kp = net.k + 1
+    ld = kp + (-kp) % (2 if prm.q_dtype == "f64" else 4)
+    Qh = np.zeros((net.n, ld))
+    Qh[:, :kp] = rng.standard_normal((net.n, kp))
+    dt = torch.float64 if prm.q_dtype == "f64" else torch.float32
+    Q = torch.from_numpy(Qh).to(dt).cuda()
+    Zg = gop.apply(Q).cpu().double().numpy()[:, :kp]
+    Qd = Q.cpu().double().numpy()[:, :kp]
+    Zr = oracle.apply_P(op_messy, Qd)
+    Zabs = oracle.apply_P(op_messy, np.abs(Qd))
+    assert (np.abs(Zg - Zr) / Zabs).max() <= (1e-12 if prm.q_dtype == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("mode", ["f32", "bf16"])
+def test_knn_near_ties_take_exact_recompute(lib, mode):
+    """24 rows equal to one base vector except that row g has coordinate g raised by 2, 3 or 4
+    units of 1/128 (all values BF16): every such row's 23 group neighbours lie within 2.6e-6
+    of one another, below the candidate scores' resolution (about 8.6e-6 at d = 32), so no 2K
+    candidate list of these rows can prove its top K and each is recomputed exactly in FP64.
+    The seeded design keeps the exact order's gaps at 4.9e-14 or more, six times the FP64 tie
+    tolerance (products of BF16 values and their sums over 32 terms are exact in FP64, so both
+    sides compute the same cosines).  The lists must equal the oracle's, order included."""
+    d, K, G = 32, 10, 24
+    rng = np.random.default_rng(43)
+    base = 1.0 + rng.choice(110, size=d, replace=False) / 128.0
+    group = np.tile(base, (G, 1))
+    group[np.arange(G), np.arange(G)] += rng.choice([2, 3, 4], size=G) / 128.0
+    bg, _ = gmm(700, d, 6, 12, "bf16" if mode == "bf16" else "f32")
+    X = np.concatenate([bg[:300], group, bg[300:]]).astype(np.float32)
+    if mode == "bf16":
+        assert np.array_equal(synth.round_to_bf16(X), X)
+    S = oracle.cosine_rows(X, np.arange(300, 300 + G))
+    top = -np.sort(-S, axis=1)
+    assert (top[:, 0] - top[:, 2 * K - 1]).max() < 3e-6
+    assert np.diff(-top[:, :2 * K + 1], axis=1).min() >= 6 * tol_for("f64", d)
+    idx, sim, st = lib.knn(upload(X, mode), K, mode)
+    gi, gs = idx.cpu().numpy(), sim.cpu().numpy()
+    print(f"{mode}: uncertified {st.uncertified_rows} recomputed {st.recomputed_rows}")
+    assert st.uncertified_rows >= G and st.recomputed_rows == st.uncertified_rows
+    swaps = check_knn_rows(X, np.arange(X.shape[0]), gi, gs, K, tol_for("f64", d))
+    assert swaps == 0
+    ref_i, _ = oracle.knn(X, K, rows=np.arange(300, 300 + G))
+    assert np.array_equal(gi[300:300 + G], ref_i)
+
+
+def test_orth_iter_takes_shifted_cholesky(lib):
+    """FP64 block whose third and fourth columns agree to 1e-9: the Gram of Z = P Q has a
+    pivot ratio near 1e-18, below the 1e-15 at which the plain Cholesky factorisation is
+    refused, so the step takes the shifted factorisation and its second pass (shifted
+    CholeskyQR3).  Q must still be the unique QR factor with positive diagonal (the oracle's
+    Householder QR), to the accuracy its condition number (about 1e9) allows."""
+    torch = torch_mod()
+    net, prm = synth.make_config(1, scale=0.5)
+    op_o, ki, ks = oracle_operator(net, prm.K, prm.beta)
+    s, keep = lib.network(net)
+    op = lib.build_operator(s, torch.from_numpy(ki.astype(np.int32)).cuda(), torch.from_numpy(ks).cuda(),
+                            prm.K, prm.beta, "f64")
+    rng = np.random.default_rng(21)
+    kp = net.k + 1
+    Q0 = rng.standard_normal((net.n, kp))
+    Q0[:, 3] = Q0[:, 2] + 1e-9 * rng.standard_normal(net.n)
+    Z = oracle.apply_P(op_o, Q0)
+    # the plain factorisation's pivots (the kernel's rule): one falls below 1e-15 of its diagonal
+    G = Z.T @ Z
+    ratios = []
+    A = G.copy()
+    for j in range(kp):
+        ratios.append(A[j, j] / G[j, j])
+        A[j + 1:, j + 1:] -= np.outer(A[j + 1:, j], A[j, j + 1:]) / A[j, j]
+    assert min(ratios) < 1e-15
+    ld = 8
+    Qt = torch.zeros((net.n, ld), dtype=torch.float64, device="cuda")
+    Qt[:, :kp] = torch.from_numpy(Q0).cuda()
+    R, dq = op.orth_iter(Qt, kp, 1)
+    Qg = Qt.cpu().numpy()[:, :kp]
+    Qr, Rr = oracle.qr_pos(Z)
+    assert np.abs(Qg.T @ Qg - np.eye(kp)).max() <= 1e-12
+    assert np.abs(Qg @ R - Z).max() <= 1e-12 * np.abs(Z).max()
+    assert np.abs(Qg[:, :3] - Qr[:, :3]).max() <= 1e-11
+    assert np.abs(Qg - Qr).max() <= 1e-5

@@ -226,6 +226,21 @@ ancka_status ancka_discretize(ancka_ctx* ctx, const void* Q, int32_t qdtype, int
                               int64_t ldq, int32_t max_iter, int32_t* labels, double* R, double* obj,
                               int32_t* iters);
 
+/* ---- Discretize without device allocation ---------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, serving loops
+ * that must not call hipMalloc, harnesses that forbid it): the same computation, arguments,
+ * results and errors as ancka_discretize, with its k x k state (R, the cluster sums and counts,
+ * the loop state; at most 98,816 bytes) in a static device array of the library instead of a
+ * context workspace.  Each GPU holds one copy of that array from ancka_create on that GPU until
+ * the process ends, and every call on that GPU uses it: calls that overlap on one GPU (from any
+ * context or stream) race and must be serialised by the caller.  The call clears the state it
+ * needs at its start, so the contents a previous call left do not matter.  It allocates
+ * nothing on the device.  Limits as ancka_discretize: 1 <= k <= 64, 1 <= n < 2^31 (no limit
+ * from the state size, which does not depend on n).  Synchronises the stream. */
+ancka_status ancka_discretize_noalloc(ancka_ctx* ctx, const void* Q, int32_t qdtype, int64_t n, int32_t k,
+                                      int64_t ldq, int32_t max_iter, int32_t* labels, double* R, double* obj,
+                                      int32_t* iters);
+
 /* ---- multi-hop conductance (Alg. 2; Eq. mhc-comp-ancka) -------------------------------------
  * phi = 1 - (1/k) trace(Yh^T F^(gamma)), F^(0) = alpha Yh, F^(l) = (1-alpha) P F^(l-1) + F^(0),
  * Yh = h(Y) from `labels` (device int32 n, values in [0,k)).  phi: host.  Synchronises. */

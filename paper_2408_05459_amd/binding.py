@@ -83,6 +83,8 @@ _SIGS = {
     "ancka_orth_iter": (C.c_int, [_VP, _VP, _VP, C.c_int64, C.c_int32, C.c_int32, _VP, _VP]),
     "ancka_discretize": (C.c_int, [_VP, _VP, C.c_int32, C.c_int64, C.c_int32, C.c_int64, C.c_int32, _VP, _VP, _VP,
                                    _VP]),
+    "ancka_discretize_noalloc": (C.c_int, [_VP, _VP, C.c_int32, C.c_int64, C.c_int32, C.c_int64, C.c_int32, _VP,
+                                           _VP, _VP, _VP]),
     "ancka_mhc": (C.c_int, [_VP, _VP, _VP, C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_double)]),
     "ancka_cluster": (C.c_int, [_VP, C.POINTER(ancka_network), C.POINTER(ancka_params), _VP, _VP,
                                 C.POINTER(ancka_report)]),
@@ -193,8 +195,9 @@ class Lib:
                                                   self.dtype_code(nbr_sim), K, beta, DTYPE_CODE[op_dtype], C.byref(h)))
         return Op(self, h, net_struct.n, op_dtype)
 
-    def discretize(self, Q, k: int, max_iter: int = 30, device=0):
-        """Q: n x (>= k) tensor view whose first k columns are the block to discretize."""
+    def discretize(self, Q, k: int, max_iter: int = 30, device=0, noalloc: bool = False):
+        """Q: n x (>= k) tensor view whose first k columns are the block to discretize.
+        noalloc: call ancka_discretize_noalloc (state in the library's static device array)."""
         import torch
         ctx = self.context(device)
         n = Q.shape[0]
@@ -202,8 +205,9 @@ class Lib:
         R = np.zeros((k, k))
         obj = C.c_double()
         it = C.c_int32()
-        self.check(ctx, self.ancka_discretize(ctx, _ptr(Q), self.dtype_code(Q), n, k, Q.stride(0), max_iter,
-                                              _ptr(labels), R.ctypes.data, C.addressof(obj), C.addressof(it)))
+        fn = self.ancka_discretize_noalloc if noalloc else self.ancka_discretize
+        self.check(ctx, fn(ctx, _ptr(Q), self.dtype_code(Q), n, k, Q.stride(0), max_iter,
+                           _ptr(labels), R.ctypes.data, C.addressof(obj), C.addressof(it)))
         return labels, R, obj.value, it.value
 
     def ws_features(self, op, X, device=0):

@@ -96,6 +96,9 @@ inline ancka_status ws_get_t(ancka_ctx* ctx, const char* name, size_t count, T**
   *out = (T*)p;
   return s;
 }
+// Looks up, once per device, the address of the Discretize state that
+// ancka_discretize_noalloc uses on the context's device (discretize.hip).
+ancka_status disc_scratch_setup(ancka_ctx* ctx);
 // allocation owned by an operator
 ancka_status op_alloc(ancka_ctx* ctx, ancka_op* op, size_t bytes, void** out);
 

@@ -86,6 +86,11 @@ ancka_status ancka_create(ancka_ctx** out, int32_t device, void* hip_stream) {
     return ANCKA_ERR_UNSUPPORTED;
   }
   c->num_cu = prop.multiProcessorCount;
+  const ancka_status ss = disc_scratch_setup(c);
+  if (ss != ANCKA_OK) {
+    delete c;
+    return ss;
+  }
   *out = c;
   return ANCKA_OK;
 }

@@ -19,6 +19,7 @@
 // cluster -- are completed deterministically: each takes the standard basis vector with the
 // largest residual against the columns before it (smaller index on ties), orthogonalised twice.
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -613,7 +614,29 @@ ancka_status disc_check_args(ancka_ctx* ctx, const char* fn, const void* Q, int3
   return ANCKA_OK;
 }
 
+// The library's own Discretize state for ancka_discretize_noalloc: one copy per GPU (a
+// device-side array), at the address hipGetSymbolAddress reports on that GPU.  Host code uses
+// only that address, never the array's name (which names host memory in host code).
+__device__ __align__(256) unsigned char scratch[DISC_STATE_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
 }  // namespace
+
+ancka_status disc_scratch_setup(ancka_ctx* ctx) {
+  if (ctx->device < 0 || ctx->device >= MAX_DEVICES)
+    return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "device %d beyond the %d devices the library tracks", ctx->device,
+                   MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[ctx->device]) {
+    void* p = nullptr;
+    HIP_TRY(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));   // the current device is ctx->device
+    g_scratch_ptr[ctx->device] = p;
+  }
+  return ANCKA_OK;
+}
 
 ancka_status discretize_internal(ancka_ctx* ctx, const void* Q, int qdtype, int64_t n, int k, int64_t ldq,
                                  int max_iter, int32_t* labels, double* R, double* obj, int32_t* iters) {
@@ -628,4 +651,18 @@ extern "C" ancka_status ancka_discretize(ancka_ctx* ctx, const void* Q, int32_t 
   ST_TRY(disc_check_args(ctx, "ancka_discretize", Q, qdtype, n, k, ldq, max_iter, labels));
   if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, ANCKA_ERR_HIP, "hipSetDevice");
   return discretize_internal(ctx, Q, qdtype, n, k, ldq, max_iter, labels, R, obj, iters);
+}
+
+extern "C" ancka_status ancka_discretize_noalloc(ancka_ctx* ctx, const void* Q, int32_t qdtype, int64_t n, int32_t k,
+                                                 int64_t ldq, int32_t max_iter, int32_t* labels, double* R,
+                                                 double* obj, int32_t* iters) {
+  ST_TRY(disc_check_args(ctx, "ancka_discretize_noalloc", Q, qdtype, n, k, ldq, max_iter, labels));
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, ANCKA_ERR_HIP, "hipSetDevice");
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    base = g_scratch_ptr[ctx->device];
+  }
+  if (!base) return set_err(ctx, ANCKA_ERR_HIP, "ancka_discretize_noalloc: no state address for device %d", ctx->device);
+  return disc_dispatch(ctx, Q, qdtype, n, k, ldq, max_iter, labels, R, obj, iters, disc_bufs_at(base));
 }

@@ -46,6 +46,23 @@ def committed_traffic(kernel: str):
         return None
 
 
+def committed_mfma(pass_name: str):
+    """MFMA utilisation counters of a BF16 KNN pass from the committed rocprofv3 summary
+    (profiles/mfma.json), or None when the kernel source changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "mfma.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        with open(os.path.join(ROOT, t["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
+                return None
+        e = t[pass_name]
+        return {"mfma_util": e["mfma_util"], "clock_ghz": e["clock_ghz"], "mfma_tflops": e["mfma_tflops"]}
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -318,7 +335,8 @@ def main():
         # the symmetric pass scores each of its pairs once: its FLOPs are all algorithmic
         roof = {"kernel": "knn_bf16_kernel, symmetric pass (similarity tiles + both rows' top-2K)",
                 "bound": "mfma", "achieved": round(sym_tf, 1), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(sym_tf / PEAK_BF16_TFLOPS, 4), "traffic": committed_traffic("knn_bf16_kernel_sym")}
+                "frac": round(sym_tf / PEAK_BF16_TFLOPS, 4), "traffic": committed_traffic("knn_bf16_kernel_sym"),
+                "counters": committed_mfma("symmetric")}
     elif tile_ms >= spmm_total_ms:
         roof = {"kernel": "knn_bf16_kernel (similarity tiles + top-2K)", "bound": "mfma",
                 "achieved": round(knn_useful_tf, 1), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
@@ -351,6 +369,7 @@ def main():
                 "uncertified_rows": last["knn_uncertified_rows"], "call_ms": round(last["knn_total_ms"], 2),
                 "window_blocks": window, "sym_ms": round(sym_ms, 2), "sym_pairs": sym_pairs,
                 "sym_tflops": round(sym_tf, 1), "handed_over": last["knn_handed_over"],
+                "mfma_counters": {p: committed_mfma(p) for p in ("bound", "window", "symmetric")},
                 "rescanned": last["knn_rescanned"]},
         "spmm": {"ms": round(spmm_ms, 3), "compulsory_bytes": spmm_bytes, "gbps_compulsory": round(spmm_gbps, 1),
                  "traffic_bytes": committed_traffic("spmm_kernel"),

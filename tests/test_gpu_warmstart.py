@@ -3,7 +3,8 @@
 The oracle mirrors the network's rounding points (BF16 operands of every product, FP32
 accumulation on the GPU, FP64 in the oracle), so the remaining differences are accumulation
 order and the rare activation whose BF16 rounding falls the other way.  Tolerances:
-  forward      relative Frobenius error of Zhat <= 1e-4, elementwise <= 2e-3 max|Zhat|;
+  forward      relative Frobenius error of Zhat <= 1e-4, elementwise <= 2e-3 max|Zhat|; against
+               the exact network (no rounding): within a first-order BF16/FP32 error bound;
   gradients    relative Frobenius error <= 1e-3 per parameter tensor;
   Adam         exact gradients (BF16-representable data), updates within 1e-6 relative;
   features     |U_gpu - U_oracle| <= 1e-6 (FP32 sums of unit-norm rows);
@@ -73,6 +74,58 @@ def test_forward_parity(lib, n, d, h1, h2, k):
         assert np.array_equal(got[i].astype(np.float64), oracle.round_bf16(P[i]))
     for i in (1, 3, 5):
         assert np.array_equal(got[i], P[i])
+
+
+def bf16_forward_bound(U, P):
+    """Elementwise bound on |Zhat_gpu - Zhat_exact|, Zhat_exact the network in exact arithmetic
+    (no rounding anywhere), for the GPU's arithmetic: every product operand rounded to BF16
+    (relative error <= u_b = 2^-9), products accumulated in FP32 (gamma_m with u = 2^-24 for m
+    terms), the bias added in FP32 (u), relu 1-Lipschitz.  First order in the errors, from the
+    exact network's magnitudes:
+      D1 = (2 u_b + u_b^2 + gamma_d (1 + u_b)^2) |U| |W1| + u |pre1|,
+      E1 = D1 + u_b (|H1| + D1)                                 (H1 rounded to BF16),
+      D2 = (1 + u_b)(E1 + gamma_h1 (|H1| + E1)) |W2| + u_b |H1| |W2| + u |pre2|,
+      E2 = D2 + u_b (|H2| + D2),
+      D3 = (1 + u_b)(E2 + gamma_h2 (|H2| + E2)) |W3| + u_b |H2| |W3| + u |Zhat|."""
+    ub, u = 2.0 ** -9, 2.0 ** -24
+
+    def gam(m):
+        return m * u / (1.0 - m * u)
+
+    W1, b1, W2, b2, W3, b3 = [np.asarray(p, np.float64) for p in P]
+    U = np.asarray(U, np.float64)
+    pre1 = U @ W1 + b1
+    H1 = np.maximum(pre1, 0.0)
+    pre2 = H1 @ W2 + b2
+    H2 = np.maximum(pre2, 0.0)
+    Z = H2 @ W3 + b3
+    D1 = (2 * ub + ub * ub + gam(U.shape[1]) * (1 + ub) ** 2) * (np.abs(U) @ np.abs(W1)) + u * np.abs(pre1)
+    E1 = D1 + ub * (H1 + D1)
+    D2 = (1 + ub) * ((E1 + gam(W2.shape[0]) * (H1 + E1)) @ np.abs(W2)) + ub * (H1 @ np.abs(W2)) + u * np.abs(pre2)
+    E2 = D2 + ub * (H2 + D2)
+    D3 = (1 + ub) * ((E2 + gam(W3.shape[0]) * (H2 + E2)) @ np.abs(W3)) + ub * (H2 @ np.abs(W3)) + u * np.abs(Z)
+    return Z, D3
+
+
+@pytest.mark.parametrize("n,d,h1,h2,k", SHAPES)
+def test_forward_against_exact_network(lib, n, d, h1, h2, k):
+    """The GPU network against the exact one (no rounding, oracle with rnd=None): every output
+    within the first-order BF16/FP32 error bound of bf16_forward_bound (times 1.05 for the
+    second-order terms), and the oracle's exact network equal to the directly computed one."""
+    from paper_2408_05459_amd import binding
+    rng = np.random.default_rng(n + d + 1)
+    U = rng.uniform(-1, 1, (n, d)).astype(np.float32)
+    P = rand_params(rng, d, h1, h2, k)
+    ws = binding.WarmStart(lib, d, h1, h2, k, seed=1)
+    ws.set(P)
+    Z = ws.forward(upload_u(U)).cpu().numpy().astype(np.float64)
+    Zx, _ = oracle.mlp_forward(U.astype(np.float64), *[p.astype(np.float64) for p in P], rnd=None)
+    Zb, B = bf16_forward_bound(U, P)
+    assert np.allclose(Zx, Zb, rtol=1e-12, atol=1e-12)
+    err = np.abs(Z - Zx)
+    print(f"n={n} d={d}: max |Z - Z_exact| {err.max():.3e}, max bound {B.max():.3e}, "
+          f"max err/bound {(err / B).max():.3f}")
+    assert (err <= 1.05 * B).all()
 
 
 @pytest.mark.parametrize("n,d,h1,h2,k", SHAPES)

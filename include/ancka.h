@@ -148,8 +148,9 @@ ancka_status ancka_device_info(ancka_ctx* ctx, int32_t* num_cu, int32_t* warp_si
  *  nbr_idx: int32 n x K (device, caller-owned).
  *  nbr_sim: n x K, double for EXACT_F64, float otherwise (device, caller-owned).
  *  stats:   host, nullable; filling it synchronises the stream.
- * Errors: INVALID_ARG unless n >= 2, d >= 1, ldx >= d, 1 <= K <= n-1 and K <= 64 (EXACT_F64) or
- * K <= 16 (the two candidate modes); UNSUPPORTED for BF16_RESCORE with a non-bf16 X or d > 512. */
+ * Errors: INVALID_ARG unless n >= 2, d >= 1, ldx >= d and 1 <= K <= min(n-1, 64) (the candidate
+ * modes keep 2K <= 128 candidates per row); UNSUPPORTED for BF16_RESCORE with a non-bf16 X or
+ * d > 512. */
 ancka_status ancka_knn(ancka_ctx* ctx, const void* X, int32_t xdtype, int64_t n, int64_t d,
                        int64_t ldx, int32_t K, int32_t mode, int32_t* nbr_idx, void* nbr_sim,
                        ancka_knn_stats* stats);

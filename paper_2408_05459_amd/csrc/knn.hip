@@ -227,16 +227,13 @@ constexpr int TAU_T = 11;  // bound pass: values kept per lane (lists up to 2 TA
 enum { SCAN_WIN = 0, SCAN_SYM = 1, SCAN_TAU = 2 };
 constexpr int NPIV = 64;   // coarse cells of the scan order
 
-// One query's candidate list in LDS, unsorted: kpp slots (the list length rounded up to 4;
-// padding slots hold (+inf, -1) and are never the worst).  The caller keeps the list's worst
-// entry (score ws, index wj, slot wp) under the order (score desc, index asc) in registers.
-// (s, jj) replaces the worst entry, then the new worst is found with 16-byte reads, eight
-// entries per step.  The list ends as the top entries of that total order whatever order
-// candidates arrive in.
-__device__ __forceinline__ void list_replace_worst(float* ls, int* li, int kpp, float s, int jj, float& ws, int& wj,
-                                                   int& wp) {
-  ls[wp] = s;
-  li[wp] = jj;
+// One query's candidate list, unsorted: kpp slots (the list length rounded up to 4; padding
+// slots hold (+inf, -1) and are never the worst), in LDS or in global memory.  The caller keeps
+// the list's worst entry (score ws, index wj, slot wp) under the order (score desc, index asc) in
+// registers.  list_worst finds it with 16-byte reads, eight entries per step; list_replace_worst
+// puts (s, jj) in its place and finds the new worst.  The list ends as the top entries of that
+// total order whatever order candidates arrive in.
+__device__ __forceinline__ void list_worst(const float* ls, const int* li, int kpp, float& ws, int& wj, int& wp) {
   float bs = INFINITY;
   int bj = INT_MIN, bp = 0;
   for (int r = 0; r < kpp; r += 8) {
@@ -262,9 +259,17 @@ __device__ __forceinline__ void list_replace_worst(float* ls, int* li, int kpp, 
   wp = bp;
 }
 
-// Arguments of both passes.  Lists are kept per sorted row p in [0, npad): KP entries sorted
-// best first, original row indices (INT_MAX: empty slot) and raw scores x_p.x_j / |x_j| (the
-// cosine times |x_p|, which orders a row's candidates like the cosine).
+__device__ __forceinline__ void list_replace_worst(float* ls, int* li, int kpp, float s, int jj, float& ws, int& wj,
+                                                   int& wp) {
+  ls[wp] = s;
+  li[wp] = jj;
+  list_worst(ls, li, kpp, ws, wj, wp);
+}
+
+// Arguments of both passes.  Lists are kept per sorted row p in [0, npad): KPP slots (KP rounded
+// up to 4; slots KP.. hold (+inf, -1)), unsorted, original row indices (INT_MAX: empty slot) and
+// raw scores x_p.x_j / |x_j| (the cosine times |x_p|, which orders a row's candidates like the
+// cosine).
 struct ScanArgs {
   const uint16_t* Xs;        // [npad][DP] bf16 rows in scan order, zero padded
   const float* invs;         // [npad] 1/|x|, 0 for zero and padding rows
@@ -277,8 +282,8 @@ struct ScanArgs {
   const int32_t* wlo;        // [nwg] window of block I: blocks wlo[I] .. whi[I] (unwrapped, taken
   const int32_t* whi;        //   mod nwg); wlo <= I <= whi, and J in I's window iff I in J's
   int KP;                    // list length
-  int32_t* lidx;             // [npad][KP] lists (written by the window pass, updated in place)
-  float* lsim;               // [npad][KP]
+  int32_t* lidx;             // [npad][KPP] lists (written by the window pass, updated in place)
+  float* lsim;               // [npad][KPP]
   float* colthr;             // [npad] candidate-side threshold: the list's worst raw score after
                              // the window pass (-inf if not full; +inf for zero and padding rows)
   const float* tile_thr;     // [ntp] smallest colthr of each tile (symmetric pass)
@@ -291,10 +296,13 @@ struct ScanArgs {
   int64_t hcap;
 };
 
-template <int DP, int QW, int NBUF, int MODE>
+// LG: the lists stay in global memory (args.lsim / args.lidx) instead of LDS, for list lengths
+// whose LDS copy would leave room for fewer than two workgroups per CU.
+template <int DP, int QW, int NBUF, int MODE, bool LG>
 __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(ScanArgs args) {
   constexpr bool SYM = MODE == SCAN_SYM;
   constexpr bool TAU = MODE == SCAN_TAU;
+  constexpr bool LDSL = !TAU && !LG;    // lists in LDS
   constexpr int KS = DP / 16;           // MFMA k-steps
   constexpr int NQB = QW / 32;          // query blocks per wave
   constexpr int QB = 4 * QW;            // queries per workgroup
@@ -312,12 +320,9 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
   float* tmn = (float*)(tperm + NBUF * BT_C);                // [NBUF] smallest norm, [2 + NBUF] tile_thr
   const int KP = args.KP;
   const int KPP = (KP + 3) & ~3;                             // list slots per query
-  float* lsim = tmn + 4;                                     // [QB][KPP]
-  int* lidx = (int*)(lsim + QB * KPP);                       // [QB][KPP]
-  float* lwv = (float*)(lidx + QB * KPP);                    // [QB] worst score of each list
-  int* lwi = (int*)(lwv + QB);                               // [QB] its index
-  int* lwp = lwi + QB;                                       // [QB] its slot
-  float* tthr = (float*)(lwp + QB);                          // [NBUF][BT_C] colthr (symmetric pass)
+  float* tthr = tmn + 4;                                     // [NBUF][BT_C] colthr (symmetric pass)
+  float* lsim = tthr + NBUF * BT_C;                          // [QB][KPP] lists in LDS (LDSL)
+  int* lidx = (int*)(lsim + (LDSL ? QB * KPP : 0));          // [QB][KPP]
 
   const int tid = threadIdx.x;
   const int wave = tid / ANCKA_WAVE;
@@ -326,37 +331,29 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
   const int half = lane / 32;
   const int64_t blk = blockIdx.x;
   const int64_t q0 = blk * QB;
+  // list of the workgroup's query q (LDS, or the global copy of its sorted row)
+  auto list_s = [&](int q) { return LDSL ? lsim + q * KPP : args.lsim + (q0 + q) * (int64_t)KPP; };
+  auto list_i = [&](int q) { return LDSL ? lidx + q * KPP : args.lidx + (q0 + q) * (int64_t)KPP; };
 
+  // the window pass starts from empty lists; the symmetric pass from the window pass's lists
   if (MODE == SCAN_WIN) {
     for (int e = tid; e < QB * KPP; e += 256) {
       const bool pad = (e % KPP) >= KP;
-      lsim[e] = pad ? INFINITY : -INFINITY;
-      lidx[e] = pad ? -1 : INT_MAX;
+      if (LDSL) {
+        lsim[e] = pad ? INFINITY : -INFINITY;
+        lidx[e] = pad ? -1 : INT_MAX;
+      } else {
+        args.lsim[q0 * KPP + e] = pad ? INFINITY : -INFINITY;
+        args.lidx[q0 * KPP + e] = pad ? -1 : INT_MAX;
+      }
     }
-    for (int q = tid; q < QB; q += 256) {
-      lwv[q] = -INFINITY;
-      lwi[q] = INT_MAX;
-      lwp[q] = 0;
-    }
-  } else if (SYM) {
-    // the window pass's lists (sorted best first): the worst entry is the first empty slot, or
-    // the last slot of a full list
+  } else if (SYM && LDSL) {
     for (int e = tid; e < QB * KPP; e += 256) {
-      const int q = e / KPP, r = e % KPP;
-      const int64_t g = (q0 + q) * KP + r;
-      lsim[e] = r < KP ? args.lsim[g] : INFINITY;
-      lidx[e] = r < KP ? args.lidx[g] : -1;
-    }
-    __syncthreads();
-    for (int q = tid; q < QB; q += 256) {
-      int r = 0;
-      while (r < KP - 1 && lidx[q * KPP + r] != INT_MAX) r++;
-      lwv[q] = lsim[q * KPP + r];
-      lwi[q] = lidx[q * KPP + r];
-      lwp[q] = r;
+      lsim[e] = args.lsim[q0 * KPP + e];
+      lidx[e] = args.lidx[q0 * KPP + e];
     }
   }
-  __syncthreads();
+  __syncthreads();   // (also orders the global initialisation of LG lists before their first reads)
 
   // query fragments: lane holds 8 bf16 of query row (l32) at k = ks*16 + half*8
   bf16x8 bq[NQB][KS];
@@ -378,12 +375,14 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
     qorig[qb] = args.perm[qs];
     const float iq = args.invs[qs];
     tq[qb] = (MODE == SCAN_WIN && args.tau) ? args.tau[qs] : -INFINITY;
-    thr[qb] = iq > 0.0f ? (SYM ? lwv[qloc[qb]] : tq[qb]) : INFINITY;
+    // worst entry of the query's list: the first empty slot of a new list; found in the window
+    // pass's list by the symmetric pass (the bound pass has no lists)
+    wv[qb] = -INFINITY;
+    wi[qb] = INT_MAX;
+    wp[qb] = 0;
+    if (SYM) list_worst(list_s(qloc[qb]), list_i(qloc[qb]), KPP, wv[qb], wi[qb], wp[qb]);
+    thr[qb] = iq > 0.0f ? (SYM ? wv[qb] : tq[qb]) : INFINITY;
     colq[qb] = iq;
-    // (the bound pass has no lists: its LDS holds only the tiles)
-    wv[qb] = TAU ? -INFINITY : lwv[qloc[qb]];
-    wi[qb] = TAU ? INT_MAX : lwi[qloc[qb]];
-    wp[qb] = TAU ? 0 : lwp[qloc[qb]];
 #pragma unroll
     for (int j = 0; j < TAU_T; j++) rt[qb][j] = -INFINITY;
 #pragma unroll
@@ -569,8 +568,8 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
       if (__ballot(hit)) {
         const int q = qloc[qb];
         const int qi = qorig[qb];
-        float* ls = lsim + q * KPP;
-        int* li = lidx + q * KPP;
+        float* ls = list_s(q);
+        int* li = list_i(q);
         for (int h = 0; h < 2; h++) {
           if (hit && half == h) {
             float tcur = wv[qb];
@@ -612,6 +611,8 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
           // take over the worst-entry record (lane l and l ^ 32 hold the same query).  LDS
           // operations of one wave execute in program order, so only the compiler must keep
           // them in order; a memory fence here would also wait for the next tile's global loads.
+          // Lists in global memory need that fence: the other half reads what this one wrote.
+          if (LG) __threadfence_block();
           {
             const float ov = __shfl_xor(wv[qb], 32, ANCKA_WAVE);
             const int oi = __shfl_xor(wi[qb], 32, ANCKA_WAVE);
@@ -707,34 +708,24 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
     }
     return;
   }
-  // sort each list (one thread per query) and store it; the window pass also stores the
-  // candidate-side threshold of the row
-  for (int q = tid; q < QB; q += 256) {
-    const int64_t qs = q0 + q;
-    float* ls = lsim + q * KPP;
-    int* li = lidx + q * KPP;
-    for (int r = 1; r < KP; r++) {
-      const float sr = ls[r];
-      const int jr = li[r];
-      int b = r;
-      while (b > 0 && better<float>(sr, jr, ls[b - 1], li[b - 1])) {
-        ls[b] = ls[b - 1];
-        li[b] = li[b - 1];
-        b--;
+  // store the lists (unsorted; the merge kernel sorts them) and, in the window pass, the
+  // candidate-side threshold of each row: the worst entry of a full list, at least the bound of
+  // the bound pass (both are lower bounds of the row's final KP-th score)
+  if (LDSL) {
+    __syncthreads();
+    for (int e = tid; e < QB * KPP; e += 256) {
+      args.lsim[q0 * KPP + e] = lsim[e];
+      args.lidx[q0 * KPP + e] = lidx[e];
+    }
+  }
+  if (!SYM) {
+#pragma unroll
+    for (int qb = 0; qb < NQB; qb++) {
+      if (half == 0) {
+        const int64_t qs = q0 + qloc[qb];
+        const float lw = wi[qb] != INT_MAX ? wv[qb] : -INFINITY;
+        args.colthr[qs] = colq[qb] > 0.0f ? fmaxf(lw, tq[qb]) : INFINITY;
       }
-      ls[b] = sr;
-      li[b] = jr;
-    }
-    for (int r = 0; r < KP; r++) {
-      args.lidx[qs * KP + r] = li[r];
-      args.lsim[qs * KP + r] = ls[r];
-    }
-    // the worst entry of a full list, at least the bound of the bound pass: both are lower bounds
-    // of the row's final KP-th score
-    if (!SYM) {
-      const float lw = li[KP - 1] != INT_MAX ? ls[KP - 1] : -INFINITY;
-      const float tb = args.tau ? args.tau[qs] : -INFINITY;
-      args.colthr[qs] = invs[qs] > 0.0f ? fmaxf(lw, tb) : INFINITY;
     }
   }
 }
@@ -765,11 +756,11 @@ __global__ void handover_starts_kernel(const uint64_t* __restrict__ hkey, int64_
   if (e == 0 || hkey[e] != hkey[e - 1]) start[hkey[e]] = e;
 }
 
-// Final lists: row p's list (sorted best first) merged with the hand-over entries of row p
-// (hkey sorted, hn entries, the first at start[p]), then written at the original index with
-// scores scaled by 1/|x_p| to cosines.  One thread per row; the result is the top KP of the
-// union under the (score, index) order, whatever order the entries arrive in.
-__global__ __launch_bounds__(256) void knn_merge_kernel(int64_t n, int KP, const int32_t* __restrict__ lidx,
+// Final lists: row p's list merged with the hand-over entries of row p (hkey sorted, hn
+// entries, the first at start[p]), sorted best first, then written at the original index with
+// scores scaled by 1/|x_p| to cosines.  One thread per row, RB rows per workgroup; the result
+// is the top KP of the union under the (score, index) order, whatever order the entries arrive in.
+__global__ __launch_bounds__(256) void knn_merge_kernel(int64_t n, int KP, int RB, const int32_t* __restrict__ lidx,
                                                         const float* __restrict__ lsim, const float* __restrict__ invs,
                                                         const int32_t* __restrict__ perm,
                                                         const uint64_t* __restrict__ hkey,
@@ -778,51 +769,46 @@ __global__ __launch_bounds__(256) void knn_merge_kernel(int64_t n, int KP, const
                                                         int32_t* __restrict__ cand_idx, float* __restrict__ cand_sim) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int KPP = (KP + 3) & ~3;
-  const int64_t p0 = (int64_t)blockIdx.x * 256;
+  const int64_t p0 = (int64_t)blockIdx.x * RB;
   const int64_t p = p0 + threadIdx.x;
   float* lsb = (float*)smem;
-  int* lib = (int*)((float*)smem + 256 * KPP);
-  // the block's 256 lists are contiguous: load them into LDS with consecutive threads on
-  // consecutive entries
-  const int64_t rows = (n - p0) < 256 ? (n - p0) : 256;
-  for (int e = threadIdx.x; e < 256 * KPP; e += 256) {
-    const int row = e / KPP, r = e % KPP;
-    const bool in = row < rows && r < KP;
-    lsb[e] = in ? lsim[(p0 + row) * KP + r] : INFINITY;
-    lib[e] = in ? lidx[(p0 + row) * KP + r] : -1;
+  int* lib = (int*)((float*)smem + RB * KPP);
+  // the block's RB lists are contiguous (KPP slots each): load them into LDS with consecutive
+  // threads on consecutive entries
+  const int64_t rows = (n - p0) < RB ? (n - p0) : RB;
+  for (int e = threadIdx.x; e < RB * KPP; e += RB) {
+    const bool in = e / KPP < rows;
+    lsb[e] = in ? lsim[p0 * KPP + e] : INFINITY;
+    lib[e] = in ? lidx[p0 * KPP + e] : -1;
   }
   __syncthreads();
   if (p >= n) return;   // no barrier below: each thread works on its own slice of LDS
   float* ls = lsb + threadIdx.x * KPP;
   int* li = lib + threadIdx.x * KPP;
-  int wp = KP - 1;
-  for (int r = 0; r < KP - 1; r++)
-    if (li[r] == INT_MAX) {
-      wp = r;
-      break;
-    }
   const int64_t e0 = hn > 0 ? start[p] : -1;
   if (e0 >= 0) {
-    float ws = ls[wp];
-    int wj = li[wp];
+    float ws;
+    int wj, wp;
+    list_worst(ls, li, KPP, ws, wj, wp);
     for (int64_t e = e0; e < hn && hkey[e] == (uint64_t)p; e++) {
       const uint64_t v = hval[e];
       const float s = __uint_as_float((uint32_t)(v & 0xffffffffu));
       const int j = (int)(v >> 32);
       if (better<float>(s, j, ws, wj)) list_replace_worst(ls, li, KPP, s, j, ws, wj, wp);
     }
-    for (int r = 1; r < KP; r++) {
-      const float sr = ls[r];
-      const int jr = li[r];
-      int b = r;
-      while (b > 0 && better<float>(sr, jr, ls[b - 1], li[b - 1])) {
-        ls[b] = ls[b - 1];
-        li[b] = li[b - 1];
-        b--;
-      }
-      ls[b] = sr;
-      li[b] = jr;
+  }
+  // (slots KP.. hold (+inf, -1) and are never replaced: the list is the first KP slots)
+  for (int r = 1; r < KP; r++) {
+    const float sr = ls[r];
+    const int jr = li[r];
+    int b = r;
+    while (b > 0 && better<float>(sr, jr, ls[b - 1], li[b - 1])) {
+      ls[b] = ls[b - 1];
+      li[b] = li[b - 1];
+      b--;
     }
+    ls[b] = sr;
+    li[b] = jr;
   }
   const int qi = perm[p];
   const float iq = invs[p];
@@ -1107,6 +1093,43 @@ __device__ __forceinline__ void wave_sort_desc(double& s, int& j, int lane) {
   }
 }
 
+// bitonic sort of 128 (s, j) pairs across a wave, two per lane: element e = slot * 64 + lane
+// (slot 0: (s0, j0), slot 1: (s1, j1)); best first in e order, so the best 64 end in slot 0
+__device__ __forceinline__ void wave_sort_desc128(double& s0, int& j0, double& s1, int& j1, int lane) {
+  for (int k = 2; k <= 128; k <<= 1) {
+    for (int st = k >> 1; st > 0; st >>= 1) {
+      if (st == 64) {
+        // partner of element e is e ^ 64: the other slot of the same lane; k = 128 (one block)
+        if (better<double>(s1, j1, s0, j0)) {
+          const double ts = s0;
+          const int tj = j0;
+          s0 = s1;
+          j0 = j1;
+          s1 = ts;
+          j1 = tj;
+        }
+        continue;
+      }
+#pragma unroll
+      for (int slot = 0; slot < 2; slot++) {
+        double& s = slot ? s1 : s0;
+        int& j = slot ? j1 : j0;
+        const int e = slot * 64 + lane;
+        const double so = __shfl_xor(s, st, 64);
+        const int jo = __shfl_xor(j, st, 64);
+        const bool up = ((e & k) == 0);
+        const bool lower = ((e & st) == 0);
+        const bool mine_better = better<double>(s, j, so, jo);
+        const bool keep = (lower == up) ? mine_better : !mine_better;
+        if (!keep) {
+          s = so;
+          j = jo;
+        }
+      }
+    }
+  }
+}
+
 template <typename TX>
 __global__ __launch_bounds__(256) void knn_rescore_kernel(const TX* __restrict__ X, int64_t n, int64_t d, int64_t ldx,
                                                           const double* __restrict__ sq, int KP, int K,
@@ -1118,8 +1141,9 @@ __global__ __launch_bounds__(256) void knn_rescore_kernel(const TX* __restrict__
   const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / ANCKA_WAVE;
   const int lane = threadIdx.x % ANCKA_WAVE;
   if (i >= n) return;
-  double my_s = -INFINITY;
-  int my_j = INT_MAX;
+  // candidate r is held by lane r % 64 in slot r / 64 (KP <= 128)
+  double my_s = -INFINITY, my_s2 = -INFINITY;
+  int my_j = INT_MAX, my_j2 = INT_MAX;
   int valid = 0;
   const double sqi = sq[i];
   const TX* xi = X + i * ldx;
@@ -1148,11 +1172,15 @@ __global__ __launch_bounds__(256) void knn_rescore_kernel(const TX* __restrict__
       if (lane == r0 + q) {
         my_s = s;
         my_j = jj[q];
+      } else if (lane + 64 == r0 + q) {
+        my_s2 = s;
+        my_j2 = jj[q];
       }
     }
   }
-  wave_sort_desc(my_s, my_j, lane);
-  if (lane < K) {
+  if (KP <= 64) wave_sort_desc(my_s, my_j, lane);
+  else wave_sort_desc128(my_s, my_j, my_s2, my_j2, lane);
+  if (lane < K) {   // K <= KP / 2 <= 64: the best K are in slot 0
     const bool ok = my_j != INT_MAX;
     nbr_idx[i * K + lane] = ok ? my_j : -1;
     nbr_sim[i * K + lane] = ok ? (float)my_s : 0.0f;
@@ -1214,18 +1242,16 @@ __global__ __launch_bounds__(256) void knn_exact_rows_kernel(const TX* __restric
   li[wave][lane] = (lane < K) ? j_l : INT_MAX;
   __syncthreads();
   if (wave == 0) {
-    // merge 4 lists of K (K <= 16 per list fits 64 lanes) -> sort -> top K
-    double s = -INFINITY;
-    int j = INT_MAX;
-    const int w = lane / 16, r = lane % 16;
-    if (r < K) {
-      s = ls[w][r];
-      j = li[w][r];
-    }
-    wave_sort_desc(s, j, lane);
+    // merge the 4 lists of K <= 64: the best 64 of lists 0 and 1, of lists 2 and 3, then of
+    // those two; the best K end in lanes 0 .. K-1 of slot 0
+    double a0 = ls[0][lane], a1 = ls[1][lane], b0 = ls[2][lane], b1 = ls[3][lane];
+    int ia0 = li[0][lane], ia1 = li[1][lane], ib0 = li[2][lane], ib1 = li[3][lane];
+    wave_sort_desc128(a0, ia0, a1, ia1, lane);
+    wave_sort_desc128(b0, ib0, b1, ib1, lane);
+    wave_sort_desc128(a0, ia0, b0, ib0, lane);
     if (lane < K) {
-      nbr_idx[i * K + lane] = (j == INT_MAX) ? -1 : j;
-      nbr_sim[i * K + lane] = (j == INT_MAX) ? 0.0f : (float)s;
+      nbr_idx[i * K + lane] = (ia0 == INT_MAX) ? -1 : ia0;
+      nbr_sim[i * K + lane] = (ia0 == INT_MAX) ? 0.0f : (float)a0;
     }
   }
 }
@@ -1234,14 +1260,10 @@ template <typename TX>
 ancka_status run_vector(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_t ldx, const double* sq,
                         const float* invn, int KP, bool f64, int32_t* cidx, void* csim) {
   const unsigned grid = (unsigned)cdiv(n, VT_Q);
-  static bool attr_set = false;
-  if (!attr_set) {
-    HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_vector_kernel<double, TX>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_vector_kernel<float, TX>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    attr_set = true;
-  }
+  HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_vector_kernel<double, TX>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_vector_kernel<float, TX>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   if (f64) {
     const size_t sm = sizeof(double) * (2 * VT_D * VT_Q + VT_Q * (VT_C + 1) + VT_Q * KP) + sizeof(int) * VT_Q * KP;
     knn_vector_kernel<double, TX><<<grid, 256, sm, ctx->stream>>>(X, n, d, ldx, sq, invn, KP, 1, cidx, (double*)csim);
@@ -1259,24 +1281,32 @@ constexpr int bf16_qb() {
 }
 int bf16_qw(int DP) { return DP <= 256 ? 64 : 32; }
 
-template <int DP, int QW, int NBUF, int MODE>
-ancka_status run_bf16_t(ancka_ctx* ctx, const ScanArgs& args) {
-  constexpr bool SYM = MODE == SCAN_SYM;
-  constexpr int QB = 4 * QW;
-  const int KPP = (args.KP + 3) & ~3;
-  const size_t sm = (size_t)NBUF * BT_C * (DP + 8) * 2 + 2 * NBUF * BT_C * 4 + 16 +
-                    (MODE == SCAN_TAU ? 0 : (size_t)QB * KPP * 8 + (size_t)QB * 12) +
-                    (SYM ? (size_t)NBUF * BT_C * 4 : 0);
-  static bool attr_set = false;
-  if (!attr_set) {
-    HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_bf16_kernel<DP, QW, NBUF, MODE>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    attr_set = true;
-  }
-  if (sm > 160 * 1024) return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "knn: LDS budget exceeded (d=%d, K'=%d)", DP, args.KP);
-  knn_bf16_kernel<DP, QW, NBUF, MODE><<<(unsigned)args.nwg, 256, sm, ctx->stream>>>(args);
+template <int DP, int QW, int NBUF, int MODE, bool LG>
+ancka_status launch_bf16(ancka_ctx* ctx, const ScanArgs& args, size_t sm) {
+  // the LDS limit is a per-device attribute of the function: set it on every call (cheap), so a
+  // context on another device sees it too
+  HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_bf16_kernel<DP, QW, NBUF, MODE, LG>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  knn_bf16_kernel<DP, QW, NBUF, MODE, LG><<<(unsigned)args.nwg, 256, sm, ctx->stream>>>(args);
   LAUNCH_CHECK(ctx);
   return ANCKA_OK;
+}
+
+template <int DP, int QW, int NBUF, int MODE>
+ancka_status run_bf16_t(ancka_ctx* ctx, const ScanArgs& args) {
+  constexpr int QB = 4 * QW;
+  const int KPP = (args.KP + 3) & ~3;
+  const size_t base = (size_t)NBUF * BT_C * (DP + 8) * 2 + 2 * NBUF * BT_C * 4 + 16 + (size_t)NBUF * BT_C * 4;
+  const size_t lists = (size_t)QB * KPP * 8;
+  // lists stay in LDS while the workgroups per CU the kernel is built for (two up to d = 128, else
+  // one) still fit; longer lists are kept in global memory
+  const size_t budget = (size_t)160 * 1024 / (DP <= 128 ? 2 : 1);
+  if constexpr (MODE == SCAN_TAU) {
+    return launch_bf16<DP, QW, NBUF, MODE, false>(ctx, args, base);
+  } else {
+    if (base + lists <= budget) return launch_bf16<DP, QW, NBUF, MODE, false>(ctx, args, base + lists);
+    return launch_bf16<DP, QW, NBUF, MODE, true>(ctx, args, base);
+  }
 }
 
 template <int MODE>
@@ -1378,14 +1408,11 @@ ancka_status bf16_scan(ancka_ctx* ctx, int DP, ScanArgs args, const std::vector<
     }
   }
   const int KPP = (args.KP + 3) & ~3;
-  static bool mattr = false;
-  if (!mattr) {
-    HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_merge_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     160 * 1024));
-    mattr = true;
-  }
-  knn_merge_kernel<<<(unsigned)cdiv(n, 256), 256, (size_t)256 * KPP * 8, ctx->stream>>>(
-      n, args.KP, args.lidx, args.lsim, args.invs, args.perm, args.hkey, args.hval, hn, hstart, cidx, csim);
+  const int RB = KPP <= 40 ? 256 : 64;   // rows per workgroup: RB lists of KPP slots in LDS
+  HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_merge_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024));
+  knn_merge_kernel<<<(unsigned)cdiv(n, RB), RB, (size_t)RB * KPP * 8, ctx->stream>>>(
+      n, args.KP, RB, args.lidx, args.lsim, args.invs, args.perm, args.hkey, args.hval, hn, hstart, cidx, csim);
   LAUNCH_CHECK(ctx);
   if (st) {
     int32_t wmax = -1;
@@ -1519,12 +1546,8 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
         }
       }
       const size_t csm = (size_t)NPIV * ((d + 7) / 8 * 8) * 2 + NPIV * 4;
-      static bool cattr = false;
-      if (!cattr) {
-        HIP_TRY(ctx, hipFuncSetAttribute((const void*)cell_assign_kernel<uint16_t>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        cattr = true;
-      }
+      HIP_TRY(ctx, hipFuncSetAttribute((const void*)cell_assign_kernel<uint16_t>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
       cell_assign_kernel<uint16_t><<<(unsigned)cdiv(n, 256), 256, csm, ctx->stream>>>(
           (const uint16_t*)(const void*)X, n, d, ldx, invn, piv, keys, nrm, order);
       LAUNCH_CHECK(ctx);
@@ -1559,8 +1582,9 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
       sa.w = scan_windows(n, nwg, QB, hcs, hlo, hhi) ? 0 : -1;
       sa.KP = KP;
 
-      ST_TRY(ws_get_t(ctx, "knn_lidx", (size_t)npad * KP, &sa.lidx));
-      ST_TRY(ws_get_t(ctx, "knn_lsim", (size_t)npad * KP, &sa.lsim));
+      const int KPP = (KP + 3) & ~3;
+      ST_TRY(ws_get_t(ctx, "knn_lidx", (size_t)npad * KPP, &sa.lidx));
+      ST_TRY(ws_get_t(ctx, "knn_lsim", (size_t)npad * KPP, &sa.lsim));
       ST_TRY(ws_get_t(ctx, "knn_colthr", (size_t)npad, &sa.colthr));
       if (sa.w >= 0) {
         int32_t *wlo = nullptr, *whi = nullptr;
@@ -1623,12 +1647,8 @@ ancka_status cell_order_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d,
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));   // hp is a stack array
   const size_t csm = (size_t)NPIV * ((d + 7) / 8 * 8) * 2 + NPIV * 4;
   if (csm > 160 * 1024) return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "cell order: d too large");
-  static bool cattr = false;
-  if (!cattr) {
-    HIP_TRY(ctx, hipFuncSetAttribute((const void*)cell_assign_kernel<TX>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     160 * 1024));
-    cattr = true;
-  }
+  HIP_TRY(ctx, hipFuncSetAttribute((const void*)cell_assign_kernel<TX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024));
   cell_assign_kernel<TX><<<(unsigned)cdiv(n, 256), 256, csm, ctx->stream>>>(X, n, d, ldx, invn, piv, keys, nrm, vals);
   LAUNCH_CHECK(ctx);
   ST_TRY(radix_sort_u64(ctx, keys, vals, n, 40));
@@ -1643,7 +1663,7 @@ extern "C" ancka_status ancka_knn(ancka_ctx* ctx, const void* X, int32_t xdtype,
                                   int32_t K, int32_t mode, int32_t* nbr_idx, void* nbr_sim, ancka_knn_stats* stats) {
   if (!ctx) return ANCKA_ERR_INVALID_ARG;
   if (!X || !nbr_idx || !nbr_sim || n < 2 || d < 1 || ldx < d || K < 1 || K > n - 1 || n > INT32_MAX - 64 ||
-      K > (mode == ANCKA_KNN_EXACT_F64 ? 64 : 16))
+      K > 64)
     return set_err(ctx, ANCKA_ERR_INVALID_ARG, "ancka_knn: invalid arguments (n=%lld d=%lld ldx=%lld K=%d)",
                    (long long)n, (long long)d, (long long)ldx, K);
   if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, ANCKA_ERR_HIP, "hipSetDevice");

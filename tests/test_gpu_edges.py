@@ -76,7 +76,7 @@ def test_knn_argument_errors(lib):
     with pytest.raises(binding.AnckaError):
         lib.knn(upload(np.ones((1, 8), dtype=np.float32), "f32"), 1, "f32")   # n < 2
     with pytest.raises(binding.AnckaError):
-        lib.knn(upload(np.ones((40, 8), dtype=np.float32), "f32"), 17, "f32")  # K > 16 in candidate modes
+        lib.knn(upload(np.ones((80, 8), dtype=np.float32), "f32"), 65, "f32")  # K > 64
 
 
 def test_mhc_rejects_labels_out_of_range(lib):
@@ -281,6 +281,53 @@ def test_knn_near_ties_take_exact_recompute(lib, mode):
     assert swaps == 0
     ref_i, _ = oracle.knn(X, K, rows=np.arange(300, 300 + G))
     assert np.array_equal(gi[300:300 + G], ref_i)
+
+
+@pytest.mark.parametrize("mode", ["f32", "bf16"])
+def test_knn_k40_near_ties_take_exact_recompute(lib, mode):
+    """K = 40 (candidate lists of 80): 90 rows equal to one base vector except for one raised
+    coordinate each (2 to 6 units of 1/128), all within 5e-6 of one another in cosine, below the
+    candidate scores' resolution at d = 96, so every one of them is recomputed exactly; the
+    recompute's four per-wave lists of 40 are merged into the final list.  BF16 values: the
+    products and their sums are exact in FP64, so both sides compute identical cosines and
+    break equal ones by index; the lists must equal the oracle's, order included."""
+    d, K, G = 96, 40, 90
+    rng = np.random.default_rng(40)
+    base = 1.0 + rng.choice(110, size=d, replace=False) / 128.0
+    group = np.tile(base, (G, 1))
+    group[np.arange(G), np.arange(G)] += rng.choice([2, 3, 4, 5, 6], size=G) / 128.0
+    bg, _ = gmm(600, d, 6, 13, "bf16")
+    X = np.concatenate([bg[:250], group, bg[250:]]).astype(np.float32)
+    assert np.array_equal(synth.round_to_bf16(X), X)
+    rows = np.arange(250, 250 + G)
+    S = oracle.cosine_rows(X, rows)
+    top = -np.sort(-S, axis=1)
+    assert (top[:, 0] - top[:, 2 * K - 1]).max() < 5e-6
+    idx, sim, st = lib.knn(upload(X, mode), K, mode)
+    gi, gs = idx.cpu().numpy(), sim.cpu().numpy()
+    print(f"{mode}: uncertified {st.uncertified_rows}")
+    assert st.uncertified_rows >= G and st.recomputed_rows == st.uncertified_rows
+    ref_i, _ = oracle.knn(X, K, rows=rows)
+    assert np.array_equal(gi[rows], ref_i)
+    check_knn_rows(X, np.arange(X.shape[0]), gi, gs, K, tol_for("f64", d))
+
+
+@pytest.mark.parametrize("mode,K", [("f32", 50), ("bf16", 50), ("f32", 64), ("bf16", 64)])
+def test_knn_long_lists(lib, mode, K):
+    """K = 50 (the paper's value for attributed graphs and multiplex graphs, Sec. 8.1) and the
+    largest K = 64: candidate lists of 100 and 128 kept in global memory by the BF16 passes,
+    rescored and certified; every row against the oracle (FP64 tie tolerance, no set
+    differences)."""
+    X, _ = gmm(1500, 128 if mode == "bf16" else 40, 8, 14, "bf16" if mode == "bf16" else "f32")
+    X = np.asarray(X, dtype=np.float32)
+    X[[3, 700]] = 0.0
+    idx, sim, st = lib.knn(upload(X, mode), K, mode)
+    gi, gs = idx.cpu().numpy(), sim.cpu().numpy()
+    print(f"{mode} K={K}: uncertified {st.uncertified_rows}")
+    assert st.zero_rows == 2 and (gi[[3, 700]] == -1).all()
+    rows = np.setdiff1d(np.arange(X.shape[0]), [3, 700])
+    swaps = check_knn_rows(X, rows, gi[rows], gs[rows], K, tol_for("f64", X.shape[1]))
+    assert swaps == 0
 
 
 def test_orth_iter_takes_shifted_cholesky(lib):

@@ -367,3 +367,34 @@ def test_cluster_op_matches_cluster(lib, cfg):
     assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
     assert ia["best_phi"] == ib["best_phi"] and ia["trace"] == ib["trace"]
     assert ib["phase_ms"]["knn"] == 0.0 and ib["phase_ms"]["operator"] == 0.0
+
+
+@pytest.mark.parametrize("cfg", [3, 4])
+def test_k50_knn_and_cluster(lib, cfg):
+    """K = 50, the paper's setting for attributed graphs and multiplex graphs (Sec. 8.1), on the
+    multiplex workload and the benchmark graph at parity scale: the KNN lists against the
+    oracle's (FP64 tie tolerance, no set differences) and the whole method against the oracle's
+    run on its own K = 50 operator (ARI, conductance, stopping point)."""
+    net, prm, _, _, _ = workload(cfg)
+    K = 50
+    op, ki, ks = oracle_operator(net, K, prm.beta)
+    from paper_2408_05459_amd.binding import upload_attributes
+    X = upload_attributes(net.X, net.x_dtype)
+    idx, sim, st = lib.knn(X, K, prm.knn_mode)
+    gi, gs = idx.cpu().numpy(), sim.cpu().numpy()
+    swaps = check_knn_rows(net.X, np.arange(net.n), gi, gs, K, tol_knn(prm, net.d))
+    assert swaps == 0
+    s, keep = lib.network(net)
+    params = lib.default_params(k=net.k, K=K, alpha=prm.alpha, beta=prm.beta, gamma=prm.gamma, tau=prm.tau,
+                                T_i=prm.T_i, T_a=prm.T_a, eps_q=prm.eps_q, knn_mode=prm.knn_mode,
+                                q_dtype=prm.q_dtype)
+    lg, info = lib.cluster(s, params)
+    lg = lg.cpu().numpy()
+    lr, rep = oracle.cluster(op, net.k, alpha=prm.alpha, gamma=prm.gamma, tau=prm.tau, T_i=prm.T_i, T_a=prm.T_a,
+                             eps_q=prm.eps_q)
+    phi_g = oracle.mhc(op, lg, net.k, prm.alpha, prm.gamma)
+    print(f"cfg {cfg} K=50: ARI {ari(lg, lr):.4f} phi gpu {phi_g:.6f} oracle {rep.best_phi:.6f}; iters gpu "
+          f"{info['iterations']} ({info['stop_reason']}) oracle {rep.iterations} ({rep.reason})")
+    assert ari(lg, lr) >= 0.99
+    assert abs(phi_g - rep.best_phi) <= 1e-4 * rep.best_phi
+    assert (info["iterations"], info["stop_reason"]) == (rep.iterations, rep.reason)

@@ -223,6 +223,31 @@ def warm_vs_cold(lib, graphs: int, n_train: int, epochs: int, lr: float, n_test:
     return res
 
 
+def gemm_reference():
+    """The vendor BF16 GEMM (torch.matmul, hipBLASLt) on the same GPU, for context: large square
+    products and the n x n x 128 shape of the KNN similarity product.  One JSON line."""
+    import torch
+    out = []
+    for M, N, K, reps in ((8192, 8192, 8192, 20), (16384, 16384, 8192, 5), (32768, 32768, 128, 10),
+                          (65536, 65536, 128, 5), (65536, 65536, 256, 5)):
+        a = torch.randn(M, K, device="cuda", dtype=torch.bfloat16)
+        b = torch.randn(N, K, device="cuda", dtype=torch.bfloat16)
+        for _ in range(3):
+            c = a @ b.T
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            c = a @ b.T
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out.append({"M": M, "N": N, "K": K, "ms": round(ms, 3), "tflops": round(2.0 * M * N * K / ms / 1e9, 1)})
+        log(f"{M}x{N}x{K}: {ms:.3f} ms, {out[-1]['tflops']} TFLOP/s")
+        del a, b, c
+    print(json.dumps({"gemm_reference_bf16": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +264,8 @@ def main():
     ap.add_argument("--ws-lr", type=float, default=1e-3)
     ap.add_argument("--ws-test-n", type=int, default=1000000)
     ap.add_argument("--ws-workers", type=int, default=host_threads())
+    ap.add_argument("--gemm-reference", action="store_true",
+                    help="only time the vendor BF16 GEMM (torch.matmul) for context, then exit")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="copy a buffer of this many MiB three times first (reference kernel for HBM counters)")
     a = ap.parse_args()
@@ -251,6 +278,9 @@ def main():
     from paper_2408_05459_amd import binding, synth
 
     torch.cuda.set_device(0)
+    if a.gemm_reference:
+        gemm_reference()
+        return
     lib = binding.load()
     if a.copy_calibration_mib > 0:
         nb = a.copy_calibration_mib << 20

@@ -264,6 +264,9 @@ def main():
     ap.add_argument("--ws-lr", type=float, default=1e-3)
     ap.add_argument("--ws-test-n", type=int, default=1000000)
     ap.add_argument("--ws-workers", type=int, default=host_threads())
+    ap.add_argument("--study", default=None, metavar="OUT.json",
+                    help="only run the parameter sweeps and convergence traces on the synthetic workloads "
+                         "(sweep.study) and write them to OUT.json, then exit")
     ap.add_argument("--gemm-reference", action="store_true",
                     help="only time the vendor BF16 GEMM (torch.matmul) for context, then exit")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -282,6 +285,15 @@ def main():
         gemm_reference()
         return
     lib = binding.load()
+    if a.study:
+        from paper_2408_05459_amd import sweep
+        t0 = time.perf_counter()
+        res = sweep.study(lib, log=log)
+        res["seconds"] = round(time.perf_counter() - t0, 1)
+        with open(a.study, "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps({"study": a.study, "seconds": res["seconds"]}), flush=True)
+        return
     if a.copy_calibration_mib > 0:
         nb = a.copy_calibration_mib << 20
         src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")

@@ -80,3 +80,19 @@ def test_warm_block_path_matches_cold_labels_format(lib):
     assert info["trace"][0][0] == 0
     lg = lab.cpu().numpy()
     assert lg.min() >= 0 and lg.max() < net.k
+
+
+def test_parameter_study_plumbing(lib):
+    """The sweep and convergence drivers on a small hypergraph: one row per value, the trace has
+    T + 1 rows, the greedy start's conductance at t = 0 is the run's phi_0."""
+    from paper_2408_05459_amd import sweep
+    rows = sweep.sweep(lib, 1, 0.2, "beta", [0.0, 0.5])
+    assert [r["beta"] for r in rows] == [0.0, 0.5] and all(0 <= r["acc"] <= 1 for r in rows)
+    tr = sweep.convergence_trace(lib, 1, 0.2, 6, start="greedy")
+    assert [r["t"] for r in tr] == list(range(7))
+    net, prm = sweep.synth.make_config(1, scale=0.2)
+    s, keep = lib.network(net)
+    _, info = lib.cluster(s, lib.default_params(k=net.k, K=prm.K, knn_mode=prm.knn_mode, q_dtype=prm.q_dtype))
+    assert abs(tr[0]["phi"] - info["trace"][0][1]) <= 1e-12 * max(1.0, info["trace"][0][1])
+    rnd = sweep.convergence_trace(lib, 1, 0.2, 3, start="random")
+    assert len(rnd) == 4

@@ -258,6 +258,9 @@ def main():
     ap.add_argument("--spmm-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start comparison")
+    ap.add_argument("--no-ivf", action="store_true", help="skip the IVF (approximate KNN) comparison")
+    ap.add_argument("--ivf-nlist", type=int, default=1024)
+    ap.add_argument("--ivf-nprobe", type=int, default=16)
     ap.add_argument("--ws-graphs", type=int, default=200)
     ap.add_argument("--ws-n", type=int, default=50000)
     ap.add_argument("--ws-epochs", type=int, default=8)
@@ -368,6 +371,42 @@ def main():
     spmm_ms = e0.elapsed_time(e1) / a.spmm_reps
     spmm_bytes = spmm_compulsory_bytes(oinfo, n, net.L, kp)
     spmm_gbps = spmm_bytes / (spmm_ms * 1e-3) / 1e9
+    # ---- IVF search (approximate) at the same size: time, recall against the exact lists above,
+    # and the whole method with IVF lists against the exact run's labels
+    ivf = None
+    if not a.no_ivf:
+        ivf = {"nlist": a.ivf_nlist, "nprobe": a.ivf_nprobe}
+        lib.knn_ivf(X, prm.K, a.ivf_nlist, a.ivf_nprobe)          # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iidx, isim, ist = lib.knn_ivf(X, prm.K, a.ivf_nlist, a.ivf_nprobe)
+        torch.cuda.synchronize()
+        ivf["knn_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+        ivf["tile_ms"] = round(ist.tile_ms, 2)
+        ivf["pairs_fraction"] = round(ist.sym_pairs / float(n) ** 2, 5)
+        hits = torch.zeros((), dtype=torch.int64, device="cuda")
+        for r0 in range(0, n, 1 << 18):
+            a_ = iidx[r0:r0 + (1 << 18)].long()
+            b_ = nidx[r0:r0 + (1 << 18)].long()
+            m = (a_[:, :, None] == b_[:, None, :]) & (b_[:, None, :] >= 0)
+            hits += m.any(dim=2).sum()
+        ivf["recall_at_K"] = round(int(hits) / float(int((nidx >= 0).sum())), 5)
+        del iidx, isim
+        pi = lib.default_params(k=net.k, K=prm.K, alpha=prm.alpha, beta=prm.beta, gamma=prm.gamma, tau=prm.tau,
+                                T_i=prm.T_i, T_a=prm.T_a, eps_q=prm.eps_q, knn_mode="ivf", q_dtype=prm.q_dtype)
+        pi.ivf_nlist, pi.ivf_nprobe = a.ivf_nlist, a.ivf_nprobe
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        li, ii = lib.cluster(s, pi)
+        torch.cuda.synchronize()
+        ivf["cluster_s"] = round(time.perf_counter() - t0, 4)
+        ivf["cluster_phases_ms"] = {k_: round(v, 1) for k_, v in ii["phase_ms"].items()}
+        ivf["ari_vs_exact_run"] = round(float(adjusted_rand_score(labels.cpu().numpy(), li.cpu().numpy())), 5)
+        ivf["best_phi"] = ii["best_phi"]
+        ivf["best_phi_exact_run"] = last["best_phi"]
+        ivf["iterations"] = ii["iterations"]
+        log(f"IVF nlist {a.ivf_nlist} nprobe {a.ivf_nprobe}: KNN {ivf['knn_ms']} ms, recall {ivf['recall_at_K']}, "
+            f"cluster {ivf['cluster_s']} s, ARI vs exact run {ivf['ari_vs_exact_run']}")
     del X, nidx, nsim, op, Q
     torch.cuda.empty_cache()
 
@@ -422,6 +461,7 @@ def main():
         "stop_reason": last["stop_reason"],
         "best_phi": last["best_phi"],
         "ari_vs_planted": round(ari_planted, 4),
+        "ivf": ivf,
     }
     if not a.no_warm:
         out["warm_start"] = warm_vs_cold(lib, a.ws_graphs, a.ws_n, a.ws_epochs, a.ws_lr, a.ws_test_n, a.ws_workers)

@@ -43,7 +43,8 @@ typedef enum { ANCKA_HYPERGRAPH = 0, ANCKA_GRAPH = 1, ANCKA_MULTIPLEX = 2 } anck
  * EXACT_F32: FP32 tiles, top-2K candidates, FP64 rescoring, certificate, exact recompute of
  * uncertified rows.  BF16_RESCORE: BF16 MFMA tiles with FP32 accumulation, then as EXACT_F32.
  * Both non-F64 modes return similarities in float. */
-typedef enum { ANCKA_KNN_EXACT_F64 = 0, ANCKA_KNN_EXACT_F32 = 1, ANCKA_KNN_BF16_RESCORE = 2 } ancka_knn_mode;
+typedef enum { ANCKA_KNN_EXACT_F64 = 0, ANCKA_KNN_EXACT_F32 = 1, ANCKA_KNN_BF16_RESCORE = 2,
+               ANCKA_KNN_IVF_BF16 = 3 /* approximate: ancka_knn_ivf (ancka_cluster only) */ } ancka_knn_mode;
 
 #define ANCKA_MAX_LAYERS 16
 
@@ -90,6 +91,8 @@ typedef struct {
   int32_t knn_mode;      /* ancka_knn_mode */
   int32_t q_dtype;       /* ANCKA_F32 or ANCKA_F64: precision of the iterated block */
   int32_t early_stop;    /* 1: apply Eqs. (tcond-1) and (tcond-2); 0: run exactly T_a iterations */
+  int32_t ivf_nlist;     /* knn_mode IVF_BF16: lists of the coarse quantiser (default 1024) */
+  int32_t ivf_nprobe;    /* knn_mode IVF_BF16: lists each query block scans (default 16) */
 } ancka_params;
 
 typedef struct {
@@ -154,6 +157,26 @@ ancka_status ancka_device_info(ancka_ctx* ctx, int32_t* num_cu, int32_t* warp_si
 ancka_status ancka_knn(ancka_ctx* ctx, const void* X, int32_t xdtype, int64_t n, int64_t d,
                        int64_t ldx, int32_t K, int32_t mode, int32_t* nbr_idx, void* nbr_sim,
                        ancka_knn_stats* stats);
+
+/* ---- approximate KNN graph: IVF coarse quantiser + exact rescoring (Alg. 6, the approximate
+ * index the paper uses beyond 100k nodes; Sec. 7, KNN construction) ---------------------------
+ * For n beyond the exact n^2 budget.  Coarse quantiser: nlist pivot rows (pivot c is the first
+ * non-zero row at or after row c n / nlist); each row belongs to the list of its most similar
+ * pivot.  Rows are grouped by list; each block of consecutive rows of a list scans, with BF16
+ * MFMA tiles, the rows of its own list(s) and of the nprobe - 1 lists whose pivots are most
+ * similar to its list's pivot, keeping the top 2K candidates per row by score; the candidates are
+ * rescored in FP64 and the top K returned by (cosine desc, index asc).  Returned similarities are
+ * exact FP64 cosines (rounded to float); the neighbour sets are approximate (a true neighbour in
+ * an unprobed list is missed).  nprobe = nlist scans every row, as the exact search does.
+ * X: bf16 n x d (ldx >= d), d <= 512.  nbr_idx: int32 n x K; nbr_sim: float n x K (device,
+ * caller-owned).  stats: host, nullable (uncertified_rows counts rows whose 2K list could not
+ * certify its top K among the scanned candidates; nothing is recomputed; sym_pairs = ordered
+ * pairs scored).  Synchronises the stream.
+ * Errors: INVALID_ARG unless 1 <= K <= min(n-1, 64), 1 <= nlist <= min(n, 4096) and
+ * 1 <= nprobe <= min(nlist, 64); UNSUPPORTED for non-bf16 X or d > 512. */
+ancka_status ancka_knn_ivf(ancka_ctx* ctx, const void* X, int32_t xdtype, int64_t n, int64_t d, int64_t ldx,
+                           int32_t K, int32_t nlist, int32_t nprobe, int32_t* nbr_idx, void* nbr_sim,
+                           ancka_knn_stats* stats);
 
 /* ---- operator P = (I - B) P_N + B P_K (Eqs. AK, beta_i, p-mat-ancka, rw-hg/ag/mg) -------
  * Builds, on the device, every structure the walk needs without forming P:

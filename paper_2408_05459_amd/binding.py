@@ -18,14 +18,15 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libancka.so
 ANCKA_OK, ANCKA_ERR_INVALID_ARG, ANCKA_ERR_UNSUPPORTED, ANCKA_ERR_OOM, ANCKA_ERR_HIP, ANCKA_ERR_NUMERICAL = range(6)
 ANCKA_F64, ANCKA_F32, ANCKA_BF16 = 0, 1, 2
 ANCKA_HYPERGRAPH, ANCKA_GRAPH, ANCKA_MULTIPLEX = 0, 1, 2
-ANCKA_KNN_EXACT_F64, ANCKA_KNN_EXACT_F32, ANCKA_KNN_BF16_RESCORE = 0, 1, 2
+ANCKA_KNN_EXACT_F64, ANCKA_KNN_EXACT_F32, ANCKA_KNN_BF16_RESCORE, ANCKA_KNN_IVF_BF16 = 0, 1, 2, 3
 ANCKA_MAX_LAYERS = 16
 ANCKA_NPHASES = 7
 PHASES = ["knn", "operator", "init", "iterations", "discretize", "mhc", "warm"]
 STOP_REASONS = ["max_iter", "converged", "early_stop"]
 
 DTYPE_CODE = {"f64": ANCKA_F64, "f32": ANCKA_F32, "bf16": ANCKA_BF16}
-KNN_MODE = {"f64": ANCKA_KNN_EXACT_F64, "f32": ANCKA_KNN_EXACT_F32, "bf16": ANCKA_KNN_BF16_RESCORE}
+KNN_MODE = {"f64": ANCKA_KNN_EXACT_F64, "f32": ANCKA_KNN_EXACT_F32, "bf16": ANCKA_KNN_BF16_RESCORE,
+            "ivf": ANCKA_KNN_IVF_BF16}
 
 
 class ancka_network(C.Structure):
@@ -39,7 +40,8 @@ class ancka_params(C.Structure):
     _fields_ = [("k", C.c_int32), ("K", C.c_int32), ("alpha", C.c_double), ("beta", C.c_double),
                 ("gamma", C.c_int32), ("tau", C.c_int32), ("T_i", C.c_int32), ("T_a", C.c_int32),
                 ("eps_q", C.c_double), ("disc_max_iter", C.c_int32), ("knn_mode", C.c_int32),
-                ("q_dtype", C.c_int32), ("early_stop", C.c_int32)]
+                ("q_dtype", C.c_int32), ("early_stop", C.c_int32), ("ivf_nlist", C.c_int32),
+                ("ivf_nprobe", C.c_int32)]
 
 
 class ancka_knn_stats(C.Structure):
@@ -73,6 +75,8 @@ _SIGS = {
     "ancka_device_info": (C.c_int, [_VP, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "ancka_knn": (C.c_int, [_VP, _VP, C.c_int32, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _VP, _VP,
                             C.POINTER(ancka_knn_stats)]),
+    "ancka_knn_ivf": (C.c_int, [_VP, _VP, C.c_int32, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
+                                C.c_int32, _VP, _VP, C.POINTER(ancka_knn_stats)]),
     "ancka_build_operator": (C.c_int, [_VP, C.POINTER(ancka_network), _VP, _VP, C.c_int32, C.c_int32, C.c_double,
                                        C.c_int32, C.POINTER(_VP)]),
     "ancka_op_destroy": (None, [_VP]),
@@ -186,6 +190,18 @@ class Lib:
         stats = ancka_knn_stats()
         self.check(ctx, self.ancka_knn(ctx, _ptr(X), self.dtype_code(X), n, d, X.stride(0), K, KNN_MODE[mode],
                                        _ptr(idx), _ptr(sim), C.byref(stats)))
+        return idx, sim, stats
+
+    def knn_ivf(self, X, K: int, nlist: int, nprobe: int, device=0):
+        """Approximate KNN lists (IVF coarse quantiser, BF16 tiles, FP64 rescoring) of bf16 X."""
+        import torch
+        ctx = self.context(device)
+        n, d = X.shape
+        idx = torch.empty((n, K), dtype=torch.int32, device=X.device)
+        sim = torch.empty((n, K), dtype=torch.float32, device=X.device)
+        stats = ancka_knn_stats()
+        self.check(ctx, self.ancka_knn_ivf(ctx, _ptr(X), self.dtype_code(X), n, d, X.stride(0), K, nlist, nprobe,
+                                           _ptr(idx), _ptr(sim), C.byref(stats)))
         return idx, sim, stats
 
     def build_operator(self, net_struct, nbr_idx, nbr_sim, K: int, beta: float, op_dtype: str, device=0):

@@ -620,7 +620,11 @@ ancka_status ancka_cluster(ancka_ctx* ctx, const ancka_network* net, const ancka
   void* nsim = nullptr;
   ST_TRY(ws_get_t(ctx, "cl_nidx", (size_t)n * p.K, &nidx));
   ST_TRY(ws_get(ctx, "cl_nsim", (size_t)n * p.K * (f64sim ? 8 : 4), &nsim));
-  ST_TRY(ancka_knn(ctx, net->X, net->xdtype, n, net->d, net->ldx, p.K, p.knn_mode, nidx, nsim, &R->knn));
+  if (p.knn_mode == ANCKA_KNN_IVF_BF16)
+    ST_TRY(ancka_knn_ivf(ctx, net->X, net->xdtype, n, net->d, net->ldx, p.K, p.ivf_nlist, p.ivf_nprobe, nidx, nsim,
+                         &R->knn));
+  else
+    ST_TRY(ancka_knn(ctx, net->X, net->xdtype, n, net->d, net->ldx, p.K, p.knn_mode, nidx, nsim, &R->knn));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   ph[ANCKA_PHASE_KNN] = now_ms() - t0;
 

@@ -128,6 +128,8 @@ ancka_params ancka_default_params(void) {
   p.knn_mode = ANCKA_KNN_EXACT_F32;
   p.q_dtype = ANCKA_F32;
   p.early_stop = 1;
+  p.ivf_nlist = 1024;
+  p.ivf_nprobe = 16;
   return p;
 }
 

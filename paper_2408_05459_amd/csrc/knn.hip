@@ -294,6 +294,10 @@ struct ScanArgs {
   uint64_t* hval;            //   (original index of the candidate << 32) | raw score bits
   unsigned long long* hcount;  // entries produced (may exceed hcap: then the buffer overflowed)
   int64_t hcap;
+  // IVF (nullable): block I scans the tiles tlist[toff[I]] .. tlist[toff[I+1] - 1] (the tiles of
+  // the cells it probes, its own cell's first) instead of a ring range; window and bound passes only
+  const int32_t* tlist;
+  const int64_t* toff;
 };
 
 // LG: the lists stay in global memory (args.lsim / args.lidx) instead of LDS, for list lengths
@@ -397,7 +401,13 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
   // loop's scalar registers from spilling
   const int ntp = (int)args.ntp;
   int ws, L, s0;
-  if (!SYM) {
+  int64_t tl0 = 0;   // IVF: this block's first entry of the tile list
+  if (!SYM && args.tlist) {
+    tl0 = args.toff[blk];
+    ws = 0;
+    L = (int)(args.toff[blk + 1] - tl0);
+    s0 = 0;
+  } else if (!SYM) {
     if (args.w < 0) {
       ws = 0;
       L = ntp;
@@ -445,6 +455,7 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
   // one reads): with no conditional load the compiler needs no wait for stale loads.
 #define KNN_TILE_AT(t)                                                                        \
   ([&](int t_) {                                                                          \
+    if (!SYM && args.tlist) return (int)args.tlist[tl0 + t_];                                 \
     int u_ = s0 + t_;                                                                         \
     if (u_ >= L) u_ -= L;                                                                     \
     u_ += ws;                                                                                 \
@@ -819,9 +830,10 @@ __global__ __launch_bounds__(256) void knn_merge_kernel(int64_t n, int KP, int R
   }
 }
 
-// cell of each row: the most similar of NPIV pivot rows (dot with the pivot scaled by its inverse
-// norm; ties to the smaller pivot).  Pivots are held in LDS as bf16; a thread owns a row and
-// sweeps it 8 elements at a time against every pivot.
+// cell of each row: the most similar of npiv pivots (dot with the pivot scaled by its inverse
+// norm; ties to the smaller pivot).  Pivots come as a bf16 matrix Pm (npiv x dp, dp = d rounded up
+// to 8, zero padded) with inverse norms pinv_g; they are held in LDS NPIV at a time; a thread owns
+// a row and sweeps it 8 elements at a time against every pivot of the chunk.
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   uint32_t b = __float_as_uint(f);
   b += 0x7FFFu + ((b >> 16) & 1u);
@@ -830,52 +842,189 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 
 template <typename TX>
 __global__ __launch_bounds__(256) void cell_assign_kernel(const TX* __restrict__ X, int64_t n, int64_t d,
-                                                          int64_t ldx, const float* __restrict__ invn,
-                                                          const int64_t* __restrict__ piv, uint64_t* __restrict__ keys,
+                                                          int64_t ldx, const uint16_t* __restrict__ Pm,
+                                                          const float* __restrict__ pinv_g, int npiv,
+                                                          uint64_t* __restrict__ keys,
                                                           const float* __restrict__ nrm, uint64_t* __restrict__ vals) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int dp = (int)((d + 7) / 8 * 8);
   uint16_t* P = (uint16_t*)smem;            // [NPIV][dp]
   float* pinv = (float*)(P + NPIV * dp);    // [NPIV]
-  for (int e = threadIdx.x; e < NPIV * dp; e += 256) {
-    const int p = e / dp, c = e % dp;
-    P[e] = (c < d) ? f32_to_bf16_rne((float)load_as_double<TX>(X, piv[p] * ldx + c)) : (uint16_t)0;
-  }
-  if (threadIdx.x < NPIV) pinv[threadIdx.x] = invn[piv[threadIdx.x]];
-  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  float acc[NPIV];
+  const TX* xr = X + (i < n ? i : 0) * ldx;
+  int best = 0;
+  float bv = -INFINITY;
+  for (int p0 = 0; p0 < npiv; p0 += NPIV) {
+    const int np = npiv - p0 < NPIV ? npiv - p0 : NPIV;
+    __syncthreads();   // the previous chunk is no longer read
+    for (int e = threadIdx.x; e < NPIV * dp; e += 256) {
+      const int p = e / dp;
+      P[e] = p < np ? Pm[(int64_t)p0 * dp + e] : (uint16_t)0;
+    }
+    if (threadIdx.x < NPIV) pinv[threadIdx.x] = threadIdx.x < np ? pinv_g[p0 + threadIdx.x] : 0.0f;
+    __syncthreads();
+    if (i < n) {
+      float acc[NPIV];
 #pragma unroll
-  for (int p = 0; p < NPIV; p++) acc[p] = 0.0f;
-  const TX* xr = X + i * ldx;
-  for (int c0 = 0; c0 < dp; c0 += 8) {
-    float xv[8];
+      for (int p = 0; p < NPIV; p++) acc[p] = 0.0f;
+      for (int c0 = 0; c0 < dp; c0 += 8) {
+        float xv[8];
 #pragma unroll
-    for (int u = 0; u < 8; u++) xv[u] = (c0 + u < d) ? (float)load_as_double<TX>(xr, c0 + u) : 0.0f;
+        for (int u = 0; u < 8; u++) xv[u] = (c0 + u < d) ? (float)load_as_double<TX>(xr, c0 + u) : 0.0f;
 #pragma unroll
-    for (int p = 0; p < NPIV; p++) {
-      const uint4 pv = *(const uint4*)(P + p * dp + c0);
-      const uint32_t w[4] = {pv.x, pv.y, pv.z, pv.w};
+        for (int p = 0; p < NPIV; p++) {
+          const uint4 pv = *(const uint4*)(P + p * dp + c0);
+          const uint32_t w[4] = {pv.x, pv.y, pv.z, pv.w};
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
-        acc[p] = fmaf(xv[2 * u], __uint_as_float(w[u] << 16), acc[p]);
-        acc[p] = fmaf(xv[2 * u + 1], __uint_as_float(w[u] & 0xffff0000u), acc[p]);
+          for (int u = 0; u < 4; u++) {
+            acc[p] = fmaf(xv[2 * u], __uint_as_float(w[u] << 16), acc[p]);
+            acc[p] = fmaf(xv[2 * u + 1], __uint_as_float(w[u] & 0xffff0000u), acc[p]);
+          }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < NPIV; p++) {
+        const float v = acc[p] * pinv[p];
+        if (p < np && (v > bv || (p0 == 0 && p == 0))) {
+          bv = v;
+          best = p0 + p;
+        }
       }
     }
   }
-  int best = 0;
-  float bv = acc[0] * pinv[0];
-#pragma unroll
-  for (int p = 1; p < NPIV; p++) {
-    const float v = acc[p] * pinv[p];
-    if (v > bv) {
-      bv = v;
-      best = p;
-    }
-  }
+  if (i >= n) return;
   keys[i] = ((uint64_t)best << 32) | (uint64_t)__float_as_uint(nrm[i]);
   vals[i] = (uint64_t)i;
+}
+
+// ---- IVF coarse quantiser (the approximate branch of Alg. 6, for n beyond the exact n^2 budget) -
+// Pivot c is the first non-zero row at or after row c n / nlist (rows are in no particular order,
+// so this is a sample of the rows); each row's list is its most similar pivot (cell_assign_kernel).
+__global__ void ivf_pivots_kernel(const float* __restrict__ invn, int64_t n, int nlist, int64_t* __restrict__ piv) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nlist) return;
+  const int64_t r0 = (int64_t)((double)c * (double)n / nlist);
+  int64_t r = r0;
+  while (r < n && !(invn[r] > 0.0f)) r++;
+  piv[c] = r < n ? r : r0;
+}
+
+// Training sample of the coarse quantiser: row s n / S of X for s < S (a sample of the rows, which
+// are in no particular order), with its inverse norm and norm
+__global__ void ivf_sample_kernel(const uint16_t* __restrict__ X, int64_t n, int64_t d, int64_t ldx, int64_t S,
+                                  const float* __restrict__ invn, const float* __restrict__ nrm,
+                                  uint16_t* __restrict__ Xsm, float* __restrict__ invs_s, float* __restrict__ nrm_s) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= S * d) return;
+  const int64_t s = e / d, c = e % d;
+  const int64_t r = (int64_t)((double)s * (double)n / (double)S);
+  Xsm[e] = X[r * ldx + c];
+  if (c == 0) {
+    invs_s[s] = invn[r];
+    nrm_s[s] = nrm[r];
+  }
+}
+
+// Pm[p] = row piv[p] of X rounded to bf16 (zero padded to dp), pinv[p] = its inverse norm
+template <typename TX>
+__global__ void gather_pivots_kernel(const TX* __restrict__ X, int64_t d, int64_t ldx, const float* __restrict__ invn,
+                                     const int64_t* __restrict__ piv, int npiv, int dp, uint16_t* __restrict__ Pm,
+                                     float* __restrict__ pinv) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)npiv * dp) return;
+  const int p = (int)(e / dp), c = (int)(e % dp);
+  Pm[e] = c < d ? f32_to_bf16_rne((float)load_as_double<TX>(X, piv[p] * ldx + c)) : (uint16_t)0;
+  if (c == 0) pinv[p] = invn[piv[p]];
+}
+
+// One Lloyd step of the spherical k-means that trains the coarse quantiser: centroid c = the
+// normalised sum of the unit rows of list c (rows order[cs[c]] .. order[cs[c+1]-1], summed in that
+// order by each column's thread), rounded to bf16, with the inverse norm of the rounded vector.
+// An empty list keeps its centroid.  One workgroup per list.
+__global__ __launch_bounds__(256) void ivf_centroid_kernel(const uint16_t* __restrict__ X, int64_t d, int64_t ldx,
+                                                           const float* __restrict__ invn,
+                                                           const uint64_t* __restrict__ order,
+                                                           const int64_t* __restrict__ cs, int dp,
+                                                           uint16_t* __restrict__ Pm, float* __restrict__ pinv) {
+  __shared__ float red[256];
+  const int c = blockIdx.x;
+  const int64_t b = cs[c], e = cs[c + 1];
+  if (e <= b) return;
+  float acc[2] = {0.0f, 0.0f};   // columns threadIdx.x and threadIdx.x + 256 (d <= 512)
+  for (int64_t p = b; p < e; p++) {
+    const int64_t r = (int64_t)order[p];
+    const float iv = invn[r];
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+      const int col = threadIdx.x + 256 * u;
+      if (col < d) acc[u] = fmaf(bf16_to_f32(X[r * ldx + col]), iv, acc[u]);
+    }
+  }
+  uint16_t q[2];
+  float sq = 0.0f;
+  red[threadIdx.x] = acc[0] * acc[0] + acc[1] * acc[1];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const float nr = sqrtf(red[0]);
+  __syncthreads();
+  if (!(nr > 0.0f)) return;
+#pragma unroll
+  for (int u = 0; u < 2; u++) {
+    const int col = threadIdx.x + 256 * u;
+    q[u] = f32_to_bf16_rne(acc[u] / nr);
+    const float v = bf16_to_f32(q[u]);
+    if (col < d) sq = fmaf(v, v, sq);
+    if (col < dp) Pm[(int64_t)c * dp + col] = col < d ? q[u] : (uint16_t)0;
+  }
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) pinv[c] = red[0] > 0.0f ? 1.0f / sqrtf(red[0]) : 0.0f;
+}
+
+// Probe lists: for pivot c, the nprobe pivots of largest cosine with it (c itself first: its
+// cosine is 1), ties to the smaller pivot.  One thread per pivot, the list in LDS.
+__global__ __launch_bounds__(64) void ivf_probe_kernel(const uint16_t* __restrict__ Pm, const float* __restrict__ pinv,
+                                                      int64_t d, int dp, int nlist, int nprobe,
+                                                      int32_t* __restrict__ probes) {
+  __shared__ float ls[64][65];
+  __shared__ int li[64][65];
+  const int c = blockIdx.x * 64 + threadIdx.x;
+  if (c >= nlist) return;
+  float* s = ls[threadIdx.x];
+  int* l = li[threadIdx.x];
+  int cnt = 0;
+  const uint16_t* xc = Pm + (int64_t)c * dp;
+  const float ic = pinv[c];
+  for (int j = 0; j < nlist; j++) {
+    float v;
+    if (j == c) {
+      v = INFINITY;   // the own cell first
+    } else {
+      const uint16_t* xj = Pm + (int64_t)j * dp;
+      float dot = 0.0f;
+      for (int64_t e = 0; e < d; e++) dot = fmaf(bf16_to_f32(xc[e]), bf16_to_f32(xj[e]), dot);
+      v = dot * ic * pinv[j];
+    }
+    // insertion into the sorted list (value desc, index asc) of at most nprobe entries
+    if (cnt < nprobe || v > s[cnt - 1]) {
+      int q = cnt < nprobe ? cnt++ : nprobe - 1;
+      while (q > 0 && v > s[q - 1]) {
+        s[q] = s[q - 1];
+        l[q] = l[q - 1];
+        q--;
+      }
+      s[q] = v;
+      l[q] = j;
+    }
+  }
+  for (int q = 0; q < nprobe; q++) probes[(int64_t)c * nprobe + q] = q < cnt ? l[q] : -1;
 }
 
 // ---- pivots of the coarse cells: farthest-point sampling -------------------------------------
@@ -1025,10 +1174,10 @@ __global__ void tile_min_sorted_kernel(const float* __restrict__ invs, int64_t n
   cinv[t] = c == INFINITY ? 0.0f : c;
 }
 
-// cs[c] = first sorted position of cell c (keys sorted by cell << 32 | norm), cs[NPIV] = n
-__global__ void cell_starts_kernel(const uint64_t* __restrict__ keys, int64_t n, int64_t* __restrict__ cs) {
-  const int c = threadIdx.x;
-  if (c > NPIV) return;
+// cs[c] = first sorted position of cell c (keys sorted by cell << 32 | norm), cs[ncell] = n
+__global__ void cell_starts_kernel(const uint64_t* __restrict__ keys, int64_t n, int ncell, int64_t* __restrict__ cs) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > ncell) return;
   const uint64_t target = (uint64_t)c << 32;
   int64_t lo = 0, hi = n;
   while (lo < hi) {
@@ -1440,7 +1589,7 @@ ancka_status bf16_scan(ancka_ctx* ctx, int DP, ScanArgs args, const std::vector<
 template <typename TX>
 ancka_status rescore_and_fix(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_t ldx, const double* sq, int KP,
                              int K, const int32_t* cidx, const float* csim, int32_t* nbr_idx, float* nbr_sim,
-                             ancka_knn_stats* st) {
+                             ancka_knn_stats* st, bool recompute = true) {
   int32_t* urows = nullptr;
   unsigned int* ucount = nullptr;
   ST_TRY(ws_get_t(ctx, "knn_urows", (size_t)n, &urows));
@@ -1455,13 +1604,13 @@ ancka_status rescore_and_fix(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, 
   unsigned int hcount = 0;
   HIP_TRY(ctx, hipMemcpyAsync(&hcount, ucount, sizeof(unsigned int), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  if (hcount > 0) {
+  if (hcount > 0 && recompute) {
     knn_exact_rows_kernel<TX><<<hcount, 256, 0, ctx->stream>>>(X, n, d, ldx, sq, K, urows, nbr_idx, nbr_sim);
     LAUNCH_CHECK(ctx);
   }
   if (st) {
     st->uncertified_rows = hcount;
-    st->recomputed_rows = hcount;
+    st->recomputed_rows = recompute ? hcount : 0;
   }
   return ANCKA_OK;
 }
@@ -1545,18 +1694,26 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
           LAUNCH_CHECK(ctx);
         }
       }
-      const size_t csm = (size_t)NPIV * ((d + 7) / 8 * 8) * 2 + NPIV * 4;
+      const int dp8 = (int)((d + 7) / 8 * 8);
+      const size_t csm = (size_t)NPIV * dp8 * 2 + NPIV * 4;
+      uint16_t* Pm = nullptr;
+      float* pinv = nullptr;
+      ST_TRY(ws_get_t(ctx, "knn_pm", (size_t)NPIV * dp8, &Pm));
+      ST_TRY(ws_get_t(ctx, "knn_pinv", NPIV, &pinv));
+      gather_pivots_kernel<uint16_t><<<(unsigned)cdiv((int64_t)NPIV * dp8, 256), 256, 0, ctx->stream>>>(
+          (const uint16_t*)(const void*)X, d, ldx, invn, piv, NPIV, dp8, Pm, pinv);
+      LAUNCH_CHECK(ctx);
       HIP_TRY(ctx, hipFuncSetAttribute((const void*)cell_assign_kernel<uint16_t>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
       cell_assign_kernel<uint16_t><<<(unsigned)cdiv(n, 256), 256, csm, ctx->stream>>>(
-          (const uint16_t*)(const void*)X, n, d, ldx, invn, piv, keys, nrm, order);
+          (const uint16_t*)(const void*)X, n, d, ldx, Pm, pinv, NPIV, keys, nrm, order);
       LAUNCH_CHECK(ctx);
       ST_TRY(radix_sort_u64(ctx, keys, order, n, 40));
       // cell ranges of the scan order (rows of a cell in norm order: a 64-row tile then spans a
       // narrow band of norms, which keeps the tile filters tight)
       int64_t* cstart = nullptr;
       ST_TRY(ws_get_t(ctx, "knn_cstart", NPIV + 1, &cstart));
-      cell_starts_kernel<<<1, 128, 0, ctx->stream>>>(keys, n, cstart);
+      cell_starts_kernel<<<1, 128, 0, ctx->stream>>>(keys, n, NPIV, cstart);
       LAUNCH_CHECK(ctx);
       int64_t hcs[NPIV + 1];
       HIP_TRY(ctx, hipMemcpyAsync(hcs, cstart, sizeof(hcs), hipMemcpyDeviceToHost, ctx->stream));
@@ -1625,6 +1782,200 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
   return ANCKA_OK;
 }
 
+// ---- IVF search (approximate; the paper's large-n branch of Alg. 6) ------------------------------
+constexpr int IVF_LLOYD = 4;     // spherical k-means steps that refine the pivot rows
+constexpr int IVF_SAMPLE = 256;  // training rows per list
+// Coarse quantiser of nlist pivot rows; rows sorted by (list, norm) form the scan order; block I of
+// QB rows scans the tiles of the lists its rows belong to and of the nprobe - 1 lists whose pivots
+// are most similar to each of those lists' pivot (own list first), with the window pass's BF16
+// tiles and top-2K lists; then FP64 rescoring of the 2K candidates and top K.  Candidates outside
+// the probed lists are never seen, so the result is approximate (no exact recompute).
+ancka_status ivf_knn(ancka_ctx* ctx, const uint16_t* X, int64_t n, int64_t d, int64_t ldx, int K, int nlist,
+                     int nprobe, int32_t* nbr_idx, float* nbr_sim, ancka_knn_stats* st) {
+  double* sq = nullptr;
+  float *invn = nullptr, *nrm = nullptr;
+  unsigned long long* zc = nullptr;
+  ST_TRY(ws_get_t(ctx, "knn_sq", (size_t)n, &sq));
+  ST_TRY(ws_get_t(ctx, "knn_invn", (size_t)n, &invn));
+  ST_TRY(ws_get_t(ctx, "knn_nrm", (size_t)n, &nrm));
+  ST_TRY(ws_get_t(ctx, "knn_zero", 2, &zc));
+  ST_TRY(fill_zero(ctx, zc, 16));
+  int DP = 32;
+  while (DP < d) DP *= 2;
+  if (DP > 512) return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "ancka_knn_ivf: d <= 512");
+  hipEvent_t* ev = nullptr;
+  ST_TRY(ctx_events(ctx, &ev));
+  HIP_TRY(ctx, hipEventRecord(ev[0], ctx->stream));
+  knn_prologue_kernel<uint16_t><<<(unsigned)cdiv(n, 4), 256, 0, ctx->stream>>>(X, n, d, ldx, sq, invn, nrm, nullptr, 0,
+                                                                               zc);
+  LAUNCH_CHECK(ctx);
+  const int KP = 2 * K;
+  const int KPP = (KP + 3) & ~3;
+  const int QB = 4 * bf16_qw(DP);
+  const int64_t nwg = cdiv(n, QB);
+  const int64_t nt = nwg * (QB / BT_C);
+  const int64_t npad = nwg * QB;
+  int64_t* piv = nullptr;
+  uint64_t *keys = nullptr, *order = nullptr;
+  int64_t* cstart = nullptr;
+  int32_t* probes = nullptr;
+  ST_TRY(ws_get_t(ctx, "ivf_piv", (size_t)nlist, &piv));
+  ST_TRY(ws_get_t(ctx, "knn_keys", (size_t)n, &keys));
+  ST_TRY(ws_get_t(ctx, "knn_order", (size_t)n, &order));
+  ST_TRY(ws_get_t(ctx, "ivf_cstart", (size_t)nlist + 1, &cstart));
+  ST_TRY(ws_get_t(ctx, "ivf_probes", (size_t)nlist * nprobe, &probes));
+  ivf_pivots_kernel<<<(unsigned)cdiv(nlist, 256), 256, 0, ctx->stream>>>(invn, n, nlist, piv);
+  LAUNCH_CHECK(ctx);
+  // coarse quantiser: the pivot rows refined by IVF_LLOYD steps of spherical k-means
+  const int dp8 = (int)((d + 7) / 8 * 8);
+  uint16_t* Pm = nullptr;
+  float* pinv = nullptr;
+  ST_TRY(ws_get_t(ctx, "ivf_pm", (size_t)nlist * dp8, &Pm));
+  ST_TRY(ws_get_t(ctx, "ivf_pinv", (size_t)nlist, &pinv));
+  gather_pivots_kernel<uint16_t><<<(unsigned)cdiv((int64_t)nlist * dp8, 256), 256, 0, ctx->stream>>>(
+      X, d, ldx, invn, piv, nlist, dp8, Pm, pinv);
+  LAUNCH_CHECK(ctx);
+  const size_t csm = (size_t)NPIV * dp8 * 2 + NPIV * 4;
+  HIP_TRY(ctx, hipFuncSetAttribute((const void*)cell_assign_kernel<uint16_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024));
+  int cbits = 1;
+  while ((1 << cbits) < nlist) cbits++;
+  // k-means steps on a training sample of IVF_SAMPLE rows per list (all rows when n is smaller)
+  const int64_t S = std::min<int64_t>(n, (int64_t)IVF_SAMPLE * nlist);
+  uint16_t* Xsm = nullptr;
+  float *invs_s = nullptr, *nrm_s = nullptr;
+  uint64_t *keys_s = nullptr, *order_s = nullptr;
+  ST_TRY(ws_get_t(ctx, "ivf_xsm", (size_t)S * d, &Xsm));
+  ST_TRY(ws_get_t(ctx, "ivf_invs_s", (size_t)S, &invs_s));
+  ST_TRY(ws_get_t(ctx, "ivf_nrm_s", (size_t)S, &nrm_s));
+  ST_TRY(ws_get_t(ctx, "ivf_keys_s", (size_t)S, &keys_s));
+  ST_TRY(ws_get_t(ctx, "ivf_order_s", (size_t)S, &order_s));
+  ivf_sample_kernel<<<(unsigned)cdiv(S * d, 256), 256, 0, ctx->stream>>>(X, n, d, ldx, S, invn, nrm, Xsm, invs_s,
+                                                                         nrm_s);
+  LAUNCH_CHECK(ctx);
+  for (int it = 0; it < IVF_LLOYD; it++) {
+    cell_assign_kernel<uint16_t><<<(unsigned)cdiv(S, 256), 256, csm, ctx->stream>>>(Xsm, S, d, d, Pm, pinv, nlist,
+                                                                                  keys_s, nrm_s, order_s);
+    LAUNCH_CHECK(ctx);
+    ST_TRY(radix_sort_u64(ctx, keys_s, order_s, S, 32 + cbits));
+    cell_starts_kernel<<<(unsigned)cdiv(nlist + 1, 256), 256, 0, ctx->stream>>>(keys_s, S, nlist, cstart);
+    LAUNCH_CHECK(ctx);
+    ivf_centroid_kernel<<<(unsigned)nlist, 256, 0, ctx->stream>>>(Xsm, d, d, invs_s, order_s, cstart, dp8, Pm, pinv);
+    LAUNCH_CHECK(ctx);
+  }
+  // every row to its list
+  cell_assign_kernel<uint16_t><<<(unsigned)cdiv(n, 256), 256, csm, ctx->stream>>>(X, n, d, ldx, Pm, pinv, nlist,
+                                                                                keys, nrm, order);
+  LAUNCH_CHECK(ctx);
+  ST_TRY(radix_sort_u64(ctx, keys, order, n, 32 + cbits));
+  cell_starts_kernel<<<(unsigned)cdiv(nlist + 1, 256), 256, 0, ctx->stream>>>(keys, n, nlist, cstart);
+  LAUNCH_CHECK(ctx);
+  ivf_probe_kernel<<<(unsigned)cdiv(nlist, 64), 64, 0, ctx->stream>>>(Pm, pinv, d, dp8, nlist, nprobe, probes);
+  LAUNCH_CHECK(ctx);
+  std::vector<int64_t> hcs(nlist + 1);
+  std::vector<int32_t> hpr((size_t)nlist * nprobe);
+  HIP_TRY(ctx, hipMemcpyAsync(hcs.data(), cstart, sizeof(int64_t) * (nlist + 1), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(hpr.data(), probes, sizeof(int32_t) * hpr.size(), hipMemcpyDeviceToHost, ctx->stream));
+  // sorted copies (bf16 rows, inverse norms, original indices) and per-tile smallest norms
+  float *tmin = nullptr, *invs = nullptr, *tcinv = nullptr;
+  int32_t* perm = nullptr;
+  uint16_t* Xs = nullptr;
+  ST_TRY(ws_get_t(ctx, "knn_tmin", (size_t)nt, &tmin));
+  ST_TRY(ws_get_t(ctx, "knn_tcinv", (size_t)nt, &tcinv));
+  ST_TRY(ws_get_t(ctx, "knn_invs", (size_t)npad, &invs));
+  ST_TRY(ws_get_t(ctx, "knn_perm", (size_t)npad, &perm));
+  ST_TRY(ws_get_t(ctx, "knn_xs", (size_t)npad * DP, &Xs));
+  gather_sorted_kernel<<<(unsigned)cdiv(npad, 4), 256, 0, ctx->stream>>>(X, n, npad, d, ldx, order, invn, DP, Xs, invs,
+                                                                         perm);
+  LAUNCH_CHECK(ctx);
+  tile_min_sorted_kernel<<<(unsigned)cdiv(nt, 256), 256, 0, ctx->stream>>>(invs, n, BT_C, tmin, tcinv, nt);
+  LAUNCH_CHECK(ctx);
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  // tile lists of the blocks: the lists of the block's rows (cells c0 .. c1), then the lists each
+  // of them probes, in probe order; each tile once
+  std::vector<int64_t> toff(nwg + 1, 0);
+  std::vector<int32_t> tl;
+  tl.reserve((size_t)nwg * nprobe * (size_t)std::max<int64_t>(1, n / nlist / BT_C + 2));
+  std::vector<int64_t> seen(nt, -1);
+  auto cell_of = [&](int64_t p) {   // last cell c with hcs[c] <= p
+    return (int)(std::upper_bound(hcs.begin(), hcs.end(), p) - hcs.begin()) - 1;
+  };
+  for (int64_t I = 0; I < nwg; I++) {
+    const int64_t p0 = I * QB, p1 = std::min(n, (I + 1) * QB) - 1;
+    const int c0 = cell_of(p0), c1 = cell_of(p1);
+    auto add_cell = [&](int c) {
+      if (c < 0 || c >= nlist || hcs[c + 1] <= hcs[c]) return;
+      for (int64_t t = hcs[c] / BT_C; t <= (hcs[c + 1] - 1) / BT_C; t++)
+        if (seen[t] != I) {
+          seen[t] = I;
+          tl.push_back((int32_t)t);
+        }
+    };
+    for (int c = c0; c <= c1; c++) add_cell(c);
+    for (int q = 1; q < nprobe; q++)
+      for (int c = c0; c <= c1; c++) add_cell(hpr[(size_t)c * nprobe + q]);
+    toff[I + 1] = (int64_t)tl.size();
+    if (toff[I + 1] == toff[I]) return set_err(ctx, ANCKA_ERR_NUMERICAL, "ancka_knn_ivf: block %lld has no tiles", (long long)I);
+  }
+  int32_t* dtl = nullptr;
+  int64_t* dtoff = nullptr;
+  ST_TRY(ws_get_t(ctx, "ivf_tlist", tl.size(), &dtl));
+  ST_TRY(ws_get_t(ctx, "ivf_toff", (size_t)nwg + 1, &dtoff));
+  HIP_TRY(ctx, hipMemcpyAsync(dtl, tl.data(), sizeof(int32_t) * tl.size(), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(ctx, hipMemcpyAsync(dtoff, toff.data(), sizeof(int64_t) * (nwg + 1), hipMemcpyHostToDevice, ctx->stream));
+  ScanArgs sa{};
+  sa.Xs = Xs;
+  sa.invs = invs;
+  sa.perm = perm;
+  sa.tile_min = tmin;
+  sa.tile_cinv = tcinv;
+  sa.nwg = nwg;
+  sa.ntp = nt;
+  sa.w = 0;
+  sa.KP = KP;
+  sa.tlist = dtl;
+  sa.toff = dtoff;
+  int32_t* wgs = nullptr;
+  ST_TRY(ws_get_t(ctx, "knn_wgs", (size_t)nwg, &wgs));
+  ST_TRY(fill_zero(ctx, wgs, sizeof(int32_t) * nwg));
+  sa.wg_start = wgs;
+  ST_TRY(ws_get_t(ctx, "knn_lidx", (size_t)npad * KPP, &sa.lidx));
+  ST_TRY(ws_get_t(ctx, "knn_lsim", (size_t)npad * KPP, &sa.lsim));
+  ST_TRY(ws_get_t(ctx, "knn_colthr", (size_t)npad, &sa.colthr));
+  if (2 * TAU_T - 1 >= KP) ST_TRY(ws_get_t(ctx, "knn_tau", (size_t)npad, &sa.tau));
+  int32_t* cidx = nullptr;
+  float* csim = nullptr;
+  ST_TRY(ws_get_t(ctx, "knn_cidx", (size_t)n * KP, &cidx));
+  ST_TRY(ws_get_t(ctx, "knn_csim", (size_t)n * KP, &csim));
+  HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
+  if (sa.tau) ST_TRY(run_bf16<SCAN_TAU>(ctx, DP, sa));
+  ST_TRY(run_bf16<SCAN_WIN>(ctx, DP, sa));
+  const int RB = KPP <= 40 ? 256 : 64;
+  HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_merge_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024));
+  knn_merge_kernel<<<(unsigned)cdiv(n, RB), RB, (size_t)RB * KPP * 8, ctx->stream>>>(
+      n, KP, RB, sa.lidx, sa.lsim, invs, perm, nullptr, nullptr, 0, nullptr, cidx, csim);
+  LAUNCH_CHECK(ctx);
+  HIP_TRY(ctx, hipEventRecord(ev[2], ctx->stream));
+  ST_TRY(rescore_and_fix<uint16_t>(ctx, X, n, d, ldx, sq, KP, K, cidx, csim, nbr_idx, nbr_sim, st, false));
+  HIP_TRY(ctx, hipEventRecord(ev[3], ctx->stream));
+  if (st) {
+    unsigned long long hz = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&hz, zc, sizeof(hz), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    st->zero_rows = (int64_t)hz;
+    float a = 0.f, b = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&a, ev[1], ev[2]));
+    HIP_TRY(ctx, hipEventElapsedTime(&b, ev[0], ev[3]));
+    st->tile_ms = a;
+    st->total_ms = b;
+    st->window = -1;
+    // pairs scored: sum over blocks of QB x 64 x tiles (ordered pairs, padding included)
+    st->sym_pairs = (int64_t)tl.size() * BT_C * QB;
+  }
+  return ANCKA_OK;
+}
+
 template <typename TX>
 ancka_status cell_order_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_t ldx, int32_t* order_out) {
   double* sq = nullptr;
@@ -1645,11 +1996,20 @@ ancka_status cell_order_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d,
   for (int p = 0; p < NPIV; p++) hp[p] = (int64_t)((double)p * (double)n / NPIV);
   HIP_TRY(ctx, hipMemcpyAsync(piv, hp, sizeof(hp), hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));   // hp is a stack array
-  const size_t csm = (size_t)NPIV * ((d + 7) / 8 * 8) * 2 + NPIV * 4;
+  const int dp8 = (int)((d + 7) / 8 * 8);
+  const size_t csm = (size_t)NPIV * dp8 * 2 + NPIV * 4;
   if (csm > 160 * 1024) return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "cell order: d too large");
+  uint16_t* Pm = nullptr;
+  float* pinv = nullptr;
+  ST_TRY(ws_get_t(ctx, "co_pm", (size_t)NPIV * dp8, &Pm));
+  ST_TRY(ws_get_t(ctx, "co_pinv", NPIV, &pinv));
+  gather_pivots_kernel<TX><<<(unsigned)cdiv((int64_t)NPIV * dp8, 256), 256, 0, ctx->stream>>>(X, d, ldx, invn, piv,
+                                                                                            NPIV, dp8, Pm, pinv);
+  LAUNCH_CHECK(ctx);
   HIP_TRY(ctx, hipFuncSetAttribute((const void*)cell_assign_kernel<TX>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    160 * 1024));
-  cell_assign_kernel<TX><<<(unsigned)cdiv(n, 256), 256, csm, ctx->stream>>>(X, n, d, ldx, invn, piv, keys, nrm, vals);
+  cell_assign_kernel<TX><<<(unsigned)cdiv(n, 256), 256, csm, ctx->stream>>>(X, n, d, ldx, Pm, pinv, NPIV, keys, nrm,
+                                                                           vals);
   LAUNCH_CHECK(ctx);
   ST_TRY(radix_sort_u64(ctx, keys, vals, n, 40));
   u64_to_i32_kernel<<<(unsigned)cdiv(n, 256), 256, 0, ctx->stream>>>(vals, n, order_out);
@@ -1677,6 +2037,22 @@ extern "C" ancka_status ancka_knn(ancka_ctx* ctx, const void* X, int32_t xdtype,
     case ANCKA_BF16: return knn_typed<uint16_t>(ctx, (const uint16_t*)X, n, d, ldx, K, mode, nbr_idx, nbr_sim, stats);
     default: return set_err(ctx, ANCKA_ERR_INVALID_ARG, "ancka_knn: unknown dtype %d", xdtype);
   }
+}
+
+extern "C" ancka_status ancka_knn_ivf(ancka_ctx* ctx, const void* X, int32_t xdtype, int64_t n, int64_t d,
+                                      int64_t ldx, int32_t K, int32_t nlist, int32_t nprobe, int32_t* nbr_idx,
+                                      void* nbr_sim, ancka_knn_stats* stats) {
+  if (!ctx) return ANCKA_ERR_INVALID_ARG;
+  if (!X || !nbr_idx || !nbr_sim || n < 2 || d < 1 || ldx < d || K < 1 || K > n - 1 || n > INT32_MAX - 64 ||
+      K > 64 || nlist < 1 || nlist > 4096 || nlist > n || nprobe < 1 || nprobe > 64 || nprobe > nlist)
+    return set_err(ctx, ANCKA_ERR_INVALID_ARG,
+                   "ancka_knn_ivf: invalid arguments (n=%lld d=%lld ldx=%lld K=%d nlist=%d nprobe=%d; need "
+                   "1 <= K <= min(n-1, 64), 1 <= nlist <= min(n, 4096), 1 <= nprobe <= min(nlist, 64))",
+                   (long long)n, (long long)d, (long long)ldx, K, nlist, nprobe);
+  if (xdtype != ANCKA_BF16) return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "ancka_knn_ivf: bf16 attributes only");
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, ANCKA_ERR_HIP, "hipSetDevice");
+  if (stats) *stats = ancka_knn_stats{0, 0, 0, 0.0, 0.0, 0.0, 0, 0, -1, 0};
+  return ivf_knn(ctx, (const uint16_t*)X, n, d, ldx, K, nlist, nprobe, nbr_idx, (float*)nbr_sim, stats);
 }
 
 ancka_status cell_order(ancka_ctx* ctx, const void* X, int xdtype, int64_t n, int64_t d, int64_t ldx, int32_t* order) {

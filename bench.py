@@ -248,6 +248,79 @@ def gemm_reference():
     print(json.dumps({"gemm_reference_bf16": out}), flush=True)
 
 
+def spmm_reference(lib, cfg: int, scale: float, reps: int = 10):
+    """The vendor sparse product (torch.sparse CSR @ dense, hipSPARSE) on the sparsity structure of
+    the walk operator P of the benchmark graph (topology rows plus KNN rows; values do not change
+    the cost), against the library's own Z = P Q on the same graph.  One JSON line."""
+    import torch
+    from paper_2408_05459_amd import binding, synth
+    net, prm = synth.make_config(cfg, scale=scale)
+    n = net.n
+    s, keep = lib.network(net)
+    X = binding.upload_attributes(net.X, net.x_dtype)
+    idx, sim, _ = lib.knn(X, prm.K, prm.knn_mode)
+    op = lib.build_operator(s, idx, sim, prm.K, prm.beta, prm.q_dtype)
+    info = op.info()
+    del X
+    kp = net.k + 1
+    Q = torch.randn((n, 64), dtype=torch.float32, device="cuda")
+    Q[:, kp:] = 0
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for _ in range(3):
+        op.apply(Q)
+    ev[0].record()
+    for _ in range(reps):
+        op.apply(Q)
+    ev[1].record()
+    torch.cuda.synchronize()
+    own_ms = ev[0].elapsed_time(ev[1]) / reps
+    # structure of P: the symmetrised topology rows, then each row's KNN neighbours (both directions)
+    ptr = torch.from_numpy(np.asarray(net.ptrs[0], dtype=np.int64)).cuda()
+    rows_t = torch.repeat_interleave(torch.arange(n, device="cuda"), ptr[1:] - ptr[:-1])
+    cols_t = torch.from_numpy(np.asarray(net.idxs[0], dtype=np.int64)).cuda()
+    ki = idx.long()
+    kr = torch.arange(n, device="cuda").repeat_interleave(prm.K)
+    kc = ki.reshape(-1)
+    ok = kc >= 0
+    r_all = torch.cat([rows_t, cols_t, kr[ok], kc[ok]])
+    c_all = torch.cat([cols_t, rows_t, kc[ok], kr[ok]])
+    key = torch.unique(r_all * n + c_all)
+    del r_all, c_all, rows_t, cols_t, kr, kc
+    rr, cc = key // n, key % n
+    crow = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    crow[1:] = torch.cumsum(torch.bincount(rr, minlength=n), 0)
+    vals = torch.rand(key.numel(), dtype=torch.float32, device="cuda")
+    P = torch.sparse_csr_tensor(crow, cc, vals, size=(n, n))
+    Qd = Q[:, :kp].contiguous()
+    for _ in range(3):
+        Z = P @ Qd
+    ev[2].record()
+    for _ in range(reps):
+        Z = P @ Qd
+    ev[3].record()
+    torch.cuda.synchronize()
+    lib_ms = ev[2].elapsed_time(ev[3]) / reps
+    # the same product as a weighted gather-sum per row (torch embedding_bag, mode 'sum')
+    import torch.nn.functional as F
+    offs = crow[:-1].contiguous()
+    for _ in range(3):
+        Z = F.embedding_bag(cc, Qd, offs, mode="sum", per_sample_weights=vals)
+    ev[2].record()
+    for _ in range(reps):
+        Z = F.embedding_bag(cc, Qd, offs, mode="sum", per_sample_weights=vals)
+    ev[3].record()
+    torch.cuda.synchronize()
+    bag_ms = ev[2].elapsed_time(ev[3]) / reps
+    out = {"workload": net.name, "nnz_P_structure": int(key.numel()), "cols": kp,
+           "own_spmm_ms": round(own_ms, 3), "torch_sparse_csr_ms": round(lib_ms, 3),
+           "torch_embedding_bag_ms": round(bag_ms, 3),
+           "own_nnz": int(info["nnz_topo"] + info["nnz_knn"]),
+           "speedup_vs_sparse_csr": round(lib_ms / own_ms, 2), "speedup_vs_embedding_bag": round(bag_ms / own_ms, 2)}
+    log(f"Z = P Q: library kernel {own_ms:.3f} ms, torch sparse CSR {lib_ms:.3f} ms, embedding_bag {bag_ms:.3f} ms "
+        f"on {key.numel()} entries")
+    print(json.dumps({"spmm_reference": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +343,9 @@ def main():
     ap.add_argument("--study", default=None, metavar="OUT.json",
                     help="only run the parameter sweeps and convergence traces on the synthetic workloads "
                          "(sweep.study) and write them to OUT.json, then exit")
+    ap.add_argument("--spmm-reference", action="store_true",
+                    help="only time the vendor sparse product (torch sparse CSR) on the operator's structure "
+                         "beside the library's Z = P Q, then exit")
     ap.add_argument("--gemm-reference", action="store_true",
                     help="only time the vendor BF16 GEMM (torch.matmul) for context, then exit")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -288,6 +364,9 @@ def main():
         gemm_reference()
         return
     lib = binding.load()
+    if a.spmm_reference:
+        spmm_reference(lib, a.config, a.scale)
+        return
     if a.study:
         from paper_2408_05459_amd import sweep
         t0 = time.perf_counter()

@@ -450,6 +450,18 @@ def main():
     spmm_ms = e0.elapsed_time(e1) / a.spmm_reps
     spmm_bytes = spmm_compulsory_bytes(oinfo, n, net.L, kp)
     spmm_gbps = spmm_bytes / (spmm_ms * 1e-3) / 1e9
+    # the same product with Q stored in BF16 (measured beside; the method keeps FP32 blocks)
+    Qb = Q.to(torch.bfloat16)
+    for _ in range(3):
+        op.apply_bf16(Qb)
+    e0.record()
+    for _ in range(a.spmm_reps):
+        op.apply_bf16(Qb)
+    e1.record()
+    torch.cuda.synchronize()
+    spmm_bf16_ms = e0.elapsed_time(e1) / a.spmm_reps
+    spmm_bf16_bytes = spmm_bytes - 2 * n * kp      # Q read at 2 bytes per element instead of 4
+    del Qb
     # ---- IVF search (approximate) at the same size: time, recall against the exact lists above,
     # and the whole method with IVF lists against the exact run's labels
     ivf = None
@@ -533,7 +545,10 @@ def main():
                 "rescanned": last["knn_rescanned"]},
         "spmm": {"ms": round(spmm_ms, 3), "compulsory_bytes": spmm_bytes, "gbps_compulsory": round(spmm_gbps, 1),
                  "traffic_bytes": committed_traffic("spmm_kernel"),
-                 "frac": round(spmm_gbps / PEAK_HBM_GBPS, 4), "nnz_topology": oinfo["nnz_topo"],
+                 "frac": round(spmm_gbps / PEAK_HBM_GBPS, 4),
+                 "bf16_block": {"ms": round(spmm_bf16_ms, 3), "compulsory_bytes": spmm_bf16_bytes,
+                                "gbps_compulsory": round(spmm_bf16_bytes / (spmm_bf16_ms * 1e-3) / 1e9, 1)},
+                 "nnz_topology": oinfo["nnz_topo"],
                  "nnz_knn": oinfo["nnz_knn"], "cols": kp},
         "phases_ms": {k_: round(v, 1) for k_, v in last["phase_ms"].items()},
         "iterations": iters,

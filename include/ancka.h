@@ -206,6 +206,16 @@ ancka_status ancka_op_info(ancka_ctx* ctx, const ancka_op* op, double* beta, int
 ancka_status ancka_apply_p(ancka_ctx* ctx, const ancka_op* op, const void* Q, void* Z, int32_t cols,
                            int64_t ld);
 
+/* The same product with the block Q stored in BF16 (half the bytes of every gathered row; the
+ * values are widened exactly and accumulated in FP32 as ancka_apply_p does): Q bf16 n x ld,
+ * Z float n x ld.  For graph and multiplex operators of FP32 values.  Measured against the FP32
+ * product on the same operator; the method itself keeps FP32 blocks (BF16 storage moves the
+ * iterated subspace by more than the 1e-4 principal-angle tolerance of the path).
+ * Errors: INVALID_ARG if cols < 1, cols > 64, ld < cols or ld % 4 != 0; UNSUPPORTED for a
+ * hypergraph or FP64 operator. */
+ancka_status ancka_apply_p_bf16(ancka_ctx* ctx, const ancka_op* op, const void* Q, float* Z, int32_t cols,
+                                int64_t ld);
+
 /* ---- greedy initial BCM (Alg. 3; Alg. 4, greedy start; Eqs. pi_c_t, argmaxlabel) ---------------
  * V_c = the k nodes of largest degree (ties: smaller index) listed by index; T_i steps of
  * Pi <- (1-alpha) Pi P_N + alpha Z_0 on the topology walk only; label of v_j = argmax_l

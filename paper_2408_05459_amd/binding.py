@@ -82,6 +82,7 @@ _SIGS = {
     "ancka_op_destroy": (None, [_VP]),
     "ancka_op_info": (C.c_int, [_VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "ancka_apply_p": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int32, C.c_int64]),
+    "ancka_apply_p_bf16": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int32, C.c_int64]),
     "ancka_init_bcm": (C.c_int, [_VP, _VP, C.c_int32, C.c_double, C.c_int32, _VP]),
     "ancka_initial_block": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int32, _VP, C.c_int64]),
     "ancka_orth_iter": (C.c_int, [_VP, _VP, _VP, C.c_int64, C.c_int32, C.c_int32, _VP, _VP]),
@@ -323,6 +324,14 @@ class Op:
         ctx = self.lib.context(device)
         Z = torch.empty_like(Q)
         self.lib.check(ctx, self.lib.ancka_apply_p(ctx, self.h, _ptr(Q), _ptr(Z), Q.shape[1], Q.stride(0)))
+        return Z
+
+    def apply_bf16(self, Qb, device=0):
+        """Z = P Q for a bf16 block Q (float Z of the same shape)."""
+        import torch
+        ctx = self.lib.context(device)
+        Z = torch.empty(Qb.shape, dtype=torch.float32, device=Qb.device)
+        self.lib.check(ctx, self.lib.ancka_apply_p_bf16(ctx, self.h, _ptr(Qb), _ptr(Z), Qb.shape[1], Qb.stride(0)))
         return Z
 
     def init_bcm(self, k: int, alpha: float, T_i: int, device=0):

@@ -54,6 +54,22 @@ __device__ __forceinline__ void vstore(T* p, const T (&v)[V16<T>::W]) {
   *(typename V16<T>::type*)p = x;
 }
 
+// a source row's W columns from coff: TS = T, or bf16 storage (TS = uint16_t, T = float: four
+// columns in one 8-byte load, widened exactly)
+template <typename T, typename TS>
+__device__ __forceinline__ void src_load(const TS* p, T (&v)[V16<T>::W]) {
+  if constexpr (sizeof(TS) == sizeof(T)) {
+    vload<T>((const T*)p, v);
+  } else {
+    static_assert(V16<T>::W == 4, "bf16 sources with FP32 blocks only");
+    const uint2 x = *(const uint2*)p;
+    v[0] = __uint_as_float(x.x << 16);
+    v[1] = __uint_as_float(x.x & 0xffff0000u);
+    v[2] = __uint_as_float(x.y << 16);
+    v[3] = __uint_as_float(x.y & 0xffff0000u);
+  }
+}
+
 enum { EPI_NONE = 0, EPI_MHC = 1, EPI_INIT = 2 };
 
 template <typename T>
@@ -103,10 +119,10 @@ __device__ __forceinline__ void onehot_row(const int32_t* __restrict__ lab, cons
   for (int c = 0; c < W; c++) v[c] = (coff + c == l) ? x : (T)0;
 }
 
-template <typename T, int LPR>
+template <typename T, int LPR, typename TS = T>
 __device__ __forceinline__ void gather_segment(const int64_t beg, const int64_t end, const int32_t* __restrict__ idx,
                                                const T* __restrict__ colw, int colw_stride, int colw_off,
-                                               const T* __restrict__ vals, const T* __restrict__ src, int64_t ld,
+                                               const T* __restrict__ vals, const TS* __restrict__ src, int64_t ld,
                                                int sub, bool col_ok, int coff, T (&acc)[V16<T>::W],
                                                const int32_t* __restrict__ olab, const T* __restrict__ oval,
                                                T oalpha) {
@@ -147,7 +163,7 @@ __device__ __forceinline__ void gather_segment(const int64_t beg, const int64_t 
         if (col_ok && olab) {
 #pragma unroll
           for (int c = 0; c < W; c++) v[q][c] = (coff + c == l[q]) ? x[q] : (T)0;
-        } else if (col_ok) vload<T>(src + (int64_t)j[q] * ld + coff, v[q]);
+        } else if (col_ok) src_load<T, TS>(src + (int64_t)j[q] * ld + coff, v[q]);
         else {
 #pragma unroll
           for (int c = 0; c < W; c++) v[q][c] = (T)0;
@@ -169,7 +185,7 @@ __device__ __forceinline__ void gather_segment(const int64_t beg, const int64_t 
 #pragma unroll
           for (int c = 0; c < W; c++) v[c] = (coff + c == l) ? x : (T)0;
         } else {
-          vload<T>(src + (int64_t)j * ld + coff, v);
+          src_load<T, TS>(src + (int64_t)j * ld + coff, v);
         }
 #pragma unroll
         for (int c = 0; c < W; c++) acc[c] = fma(w, v[c], acc[c]);
@@ -178,7 +194,9 @@ __device__ __forceinline__ void gather_segment(const int64_t beg, const int64_t 
   }
 }
 
-template <typename T, int LPR>
+// TS: storage type of the gathered sources (T, or bf16 for FP32 blocks; the pointers of A are then
+// bf16 arrays of the same leading dimensions)
+template <typename T, int LPR, typename TS = T>
 __global__ __launch_bounds__(256) void spmm_kernel(const SpmmArgs<T> A) {
   constexpr int W = V16<T>::W;
   constexpr int RPB = 256 / LPR;
@@ -199,22 +217,22 @@ __global__ __launch_bounds__(256) void spmm_kernel(const SpmmArgs<T> A) {
     T part[W];
 #pragma unroll
     for (int c = 0; c < W; c++) part[c] = (T)0;
-    gather_segment<T, LPR>(b, e, A.tidx, A.tcol, A.segs, l, nullptr, A.tsrc, A.tld, sub, col_ok, coff, part,
-                           A.oh_t ? A.oh_lab : nullptr, A.oh_val, A.oh_alpha);
+    gather_segment<T, LPR, TS>(b, e, A.tidx, A.tcol, A.segs, l, nullptr, (const TS*)A.tsrc, A.tld, sub, col_ok, coff,
+                               part, A.oh_t ? A.oh_lab : nullptr, A.oh_val, A.oh_alpha);
     const T s = A.tscale ? A.tscale[seg] : (T)1;
 #pragma unroll
     for (int c = 0; c < W; c++) acc[c] = fma(s, part[c], acc[c]);
   }
   if (A.kptr) {
-    gather_segment<T, LPR>(A.kptr[r], A.kptr[r + 1], A.kidx, nullptr, 0, 0, A.kval, A.ksrc, A.ld, sub, col_ok, coff,
-                           acc, A.oh_lab, A.oh_val, A.oh_alpha);
+    gather_segment<T, LPR, TS>(A.kptr[r], A.kptr[r + 1], A.kidx, nullptr, 0, 0, A.kval, (const TS*)A.ksrc, A.ld, sub,
+                               col_ok, coff, acc, A.oh_lab, A.oh_val, A.oh_alpha);
   }
   if ((A.ssrc || A.oh_lab) && col_ok && (A.self || A.selfu != (T)0)) {
     const T sc = A.self ? A.self[r] : A.selfu;
     if (sc != (T)0) {
       T v[W];
       if (A.oh_lab) onehot_row<T>(A.oh_lab, A.oh_val, A.oh_alpha, r, coff, v);
-      else vload<T>(A.ssrc + r * A.ld + coff, v);
+      else src_load<T, TS>((const TS*)A.ssrc + r * A.ld + coff, v);
 #pragma unroll
       for (int c = 0; c < W; c++) acc[c] = fma(sc, v[c], acc[c]);
     }
@@ -235,7 +253,7 @@ __global__ __launch_bounds__(256) void spmm_kernel(const SpmmArgs<T> A) {
   vstore<T>(A.out + r * A.ld + coff, o);
 }
 
-template <typename T>
+template <typename T, typename TS = T>
 ancka_status launch_spmm(ancka_ctx* ctx, SpmmArgs<T> A) {
   if (A.rows <= 0) return ANCKA_OK;
   constexpr int W = V16<T>::W;
@@ -245,12 +263,12 @@ ancka_status launch_spmm(ancka_ctx* ctx, SpmmArgs<T> A) {
   if (lpr > 64) return set_err(ctx, ANCKA_ERR_INVALID_ARG, "spmm: %d columns exceed one wave", A.cols);
   const unsigned grid = (unsigned)cdiv(A.rows, 256 / lpr);
   switch (lpr) {
-    case 2: spmm_kernel<T, 2><<<grid, 256, 0, ctx->stream>>>(A); break;
-    case 4: spmm_kernel<T, 4><<<grid, 256, 0, ctx->stream>>>(A); break;
-    case 8: spmm_kernel<T, 8><<<grid, 256, 0, ctx->stream>>>(A); break;
-    case 16: spmm_kernel<T, 16><<<grid, 256, 0, ctx->stream>>>(A); break;
-    case 32: spmm_kernel<T, 32><<<grid, 256, 0, ctx->stream>>>(A); break;
-    default: spmm_kernel<T, 64><<<grid, 256, 0, ctx->stream>>>(A); break;
+    case 2: spmm_kernel<T, 2, TS><<<grid, 256, 0, ctx->stream>>>(A); break;
+    case 4: spmm_kernel<T, 4, TS><<<grid, 256, 0, ctx->stream>>>(A); break;
+    case 8: spmm_kernel<T, 8, TS><<<grid, 256, 0, ctx->stream>>>(A); break;
+    case 16: spmm_kernel<T, 16, TS><<<grid, 256, 0, ctx->stream>>>(A); break;
+    case 32: spmm_kernel<T, 32, TS><<<grid, 256, 0, ctx->stream>>>(A); break;
+    default: spmm_kernel<T, 64, TS><<<grid, 256, 0, ctx->stream>>>(A); break;
   }
   LAUNCH_CHECK(ctx);
   return ANCKA_OK;
@@ -395,6 +413,25 @@ ancka_status op_apply(ancka_ctx* ctx, const ancka_op* op, const void* Q, void* Z
   return apply_typed<float>(ctx, op, (const float*)Q, (float*)Z, cols, ld, 1.0f, EPI_NONE, nullptr, nullptr, 0.0f);
 }
 
+// Z = P Q with Q stored in bf16 (graph / multiplex operators of FP32 values; FP32 accumulation)
+ancka_status op_apply_bf16(ancka_ctx* ctx, const ancka_op* op, const uint16_t* Q, float* Z, int cols, int64_t ld) {
+  SpmmArgs<float> S = blank<float>(op->n, Z, ld, cols);
+  S.segs = op->L;
+  S.tptr = op->tptr;
+  S.rorder = op->rorder;
+  S.tidx = op->tidx;
+  S.tscale = (const float*)op->tscale;
+  S.tsrc = (const float*)(const void*)Q;
+  S.kptr = op->kptr;
+  S.kidx = op->kidx;
+  S.kval = (const float*)op->kval;
+  S.ksrc = (const float*)(const void*)Q;
+  S.self = (const float*)op->self;
+  S.ssrc = (const float*)(const void*)Q;
+  S.a = 1.0f;
+  return launch_spmm<float, uint16_t>(ctx, S);
+}
+
 ancka_status op_apply_mhc(ancka_ctx* ctx, const ancka_op* op, const void* Q, void* Z, int cols, int64_t ld,
                           double alpha, const int32_t* labels, const int32_t* counts, const void* f0val) {
   // Q null: the source is F(0) = alpha Yh, row j holding f0val[j] in column labels[j]
@@ -467,4 +504,16 @@ extern "C" ancka_status ancka_apply_p(ancka_ctx* ctx, const ancka_op* op, const 
                    (long long)ld, vw);
   if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, ANCKA_ERR_HIP, "hipSetDevice");
   return op_apply(ctx, op, Q, Z, cols, ld);
+}
+
+extern "C" ancka_status ancka_apply_p_bf16(ancka_ctx* ctx, const ancka_op* op, const void* Q, float* Z, int32_t cols,
+                                           int64_t ld) {
+  if (!ctx || !op || !Q || !Z) return ANCKA_ERR_INVALID_ARG;
+  if (cols < 1 || cols > 64 || ld < cols || ld % 4 != 0)
+    return set_err(ctx, ANCKA_ERR_INVALID_ARG, "ancka_apply_p_bf16: cols=%d ld=%lld (ld must be a multiple of 4)",
+                   cols, (long long)ld);
+  if (op->dtype != ANCKA_F32 || op->kind == ANCKA_HYPERGRAPH)
+    return set_err(ctx, ANCKA_ERR_UNSUPPORTED, "ancka_apply_p_bf16: FP32 graph or multiplex operators only");
+  if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, ANCKA_ERR_HIP, "hipSetDevice");
+  return op_apply_bf16(ctx, op, (const uint16_t*)Q, Z, cols, ld);
 }

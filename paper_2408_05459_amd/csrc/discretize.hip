@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void disc_pass_kernel(const T* __restrict__ Q,
                                                         const DiscState* __restrict__ st, double fscale) {
   if (st->done) return;
   __shared__ __align__(16) T Rs[KM][KM];   // Rs[j][c] = R[c][j] (zero outside k x k)
-  __shared__ unsigned long long Ss[KM * KM];
+  __shared__ unsigned long long Ss[KM * KM];   // Ss[c][label]: lanes of different labels hit different banks
   __shared__ unsigned int cs[KM];
   const int tid = threadIdx.x;
   for (int e = tid; e < KM * KM; e += 256) {
@@ -135,13 +135,13 @@ __global__ __launch_bounds__(256) void disc_pass_kernel(const T* __restrict__ Q,
     for (int c = 0; c < KM; c++)
       if (c < k) {
         const long long f = llrint((double)q[c] * fscale);
-        if (f != 0) atomicAdd(&Ss[best * KM + c], (unsigned long long)f);
+        if (f != 0) atomicAdd(&Ss[c * KM + best], (unsigned long long)f);
       }
   }
   __syncthreads();
   for (int e = tid; e < k * k; e += 256) {
     const int a = e / k, b = e % k;
-    const unsigned long long v = Ss[a * KM + b];
+    const unsigned long long v = Ss[b * KM + a];
     if (v != 0ull) atomicAdd(&Sg[e], v);
   }
   if (tid < k && cs[tid] != 0u) atomicAdd(&cg[tid], cs[tid]);

@@ -444,12 +444,13 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
     goff[u] = r * DP + c8 * 8;
     loff[u] = r * LDR + c8 * 8;
   }
-  // Two register sets of prefetched tiles (a native vector type: the HIP uint4 struct keeps
-  // such arrays out of registers).  Set s holds the tiles of steps s+1, s+3, ...: step t commits
-  // set t&1 to LDS and reloads it with tile t+3, so each load has two steps to arrive.
-  u32x4 pre[2][CPT];
-  float pre_inv[2], pre_tmn[2], pre_thr[2], pre_tthr[2];
-  int pre_perm[2];
+  // One register set of the prefetched tile (a native vector type: the HIP uint4 struct keeps
+  // such arrays out of registers): step t commits tile t+1 to LDS after its epilogue and then
+  // loads tile t+2, so each load has a whole step to arrive.  (A second set, two steps ahead,
+  // costs 20 VGPRs and was slower.)
+  u32x4 pre[CPT];
+  float pre_inv, pre_tmn, pre_thr, pre_tthr;
+  int pre_perm;
   // tile of step t of this workgroup's scan: ws + ((s0 + t) mod L), taken mod ntp.  Every step
   // prefetches and commits a tile (past the end the last tile is loaded again, into a buffer no
   // one reads): with no conditional load the compiler needs no wait for stale loads.
@@ -462,46 +463,45 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
     return u_ >= ntp ? u_ - ntp : u_;                                                         \
   })(t)
 #define KNN_STEP_CLAMP(x) ((x) < L ? (x) : (L > 0 ? L - 1 : 0))
-#define KNN_PREFETCH(S, tt)                                                                   \
+#define KNN_PREFETCH(tt)                                                                      \
   {                                                                                           \
     const int tt_ = (tt);                                                                     \
-    pre_tmn[S] = tile_min[tt_];                                                               \
-    if (SYM) pre_tthr[S] = args.tile_thr[tt_];                                                \
-    if (TAU) pre_tthr[S] = args.tile_cinv[tt_];                                               \
+    pre_tmn = tile_min[tt_];                                                                  \
+    if (SYM) pre_tthr = args.tile_thr[tt_];                                                   \
+    if (TAU) pre_tthr = args.tile_cinv[tt_];                                                  \
     const uint16_t* src_ = Xs + tt_ * (int64_t)(BT_C * DP);                                   \
-    _Pragma("unroll") for (int u = 0; u < CPT; u++) pre[S][u] = *(const u32x4*)(src_ + goff[u]); \
+    _Pragma("unroll") for (int u = 0; u < CPT; u++) pre[u] = *(const u32x4*)(src_ + goff[u]); \
     const int r_ = tt_ * BT_C + (tid & (BT_C - 1));                                           \
-    pre_inv[S] = invs[r_];                                                                    \
-    pre_perm[S] = perm[r_];                                                                   \
-    if (SYM) pre_thr[S] = args.colthr[r_];                                                    \
+    pre_inv = invs[r_];                                                                       \
+    pre_perm = perm[r_];                                                                      \
+    if (SYM) pre_thr = args.colthr[r_];                                                       \
   }
-#define KNN_COMMIT(S, b)                                                                      \
+#define KNN_COMMIT(b)                                                                         \
   {                                                                                           \
     const int b_ = (b);                                                                       \
     uint16_t* dst_ = tileb + b_ * BT_C * LDR;                                                 \
-    _Pragma("unroll") for (int u = 0; u < CPT; u++) *(u32x4*)(dst_ + loff[u]) = pre[S][u];    \
+    _Pragma("unroll") for (int u = 0; u < CPT; u++) *(u32x4*)(dst_ + loff[u]) = pre[u];       \
     if (tid < BT_C) {                                                                         \
-      tinv[b_ * BT_C + tid] = pre_inv[S];                                                     \
-      tperm[b_ * BT_C + tid] = pre_perm[S];                                                   \
-      if (SYM) tthr[b_ * BT_C + tid] = pre_thr[S];                                            \
+      tinv[b_ * BT_C + tid] = pre_inv;                                                        \
+      tperm[b_ * BT_C + tid] = pre_perm;                                                      \
+      if (SYM) tthr[b_ * BT_C + tid] = pre_thr;                                               \
     }                                                                                         \
     if (tid == 0) {                                                                           \
-      tmn[b_] = pre_tmn[S];                                                                   \
-      if (SYM || TAU) tmn[2 + b_] = pre_tthr[S];                                              \
+      tmn[b_] = pre_tmn;                                                                      \
+      if (SYM || TAU) tmn[2 + b_] = pre_tthr;                                                 \
     }                                                                                         \
   }
 
-  // step 0's tile to buffer 0; the tiles of steps 1 and 2 in flight
-  KNN_PREFETCH(0, KNN_TILE_AT(0));
-  KNN_COMMIT(0, 0);
-  KNN_PREFETCH(0, KNN_TILE_AT(KNN_STEP_CLAMP(1)));
-  KNN_PREFETCH(1, KNN_TILE_AT(KNN_STEP_CLAMP(2)));
+  // step 0's tile to buffer 0; the tile of step 1 in flight
+  KNN_PREFETCH(KNN_TILE_AT(0));
+  KNN_COMMIT(0);
+  KNN_PREFETCH(KNN_TILE_AT(KNN_STEP_CLAMP(1)));
   __syncthreads();
 
-  // steps in pairs, so that register set s of step t = t0 + s is a compile-time index; an odd
+  // steps in pairs, so that the LDS buffer s of step t = t0 + s is a compile-time index; an odd
   // last step is followed by one whose epilogue is skipped
   int t0 = 0;
-  // the step body, inlined twice per pass of the loop below with its register set s fixed
+  // the step body, inlined twice per pass of the loop below with its buffer s fixed
   auto step = [&](auto s_tag) __attribute__((always_inline)) {
     constexpr int s = decltype(s_tag)::value;
     const int t = t0 + s;
@@ -516,20 +516,34 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
         for (int i = 0; i < 16; i++) acc[cb][qb][i] = 0.0f;
 
     const uint16_t* tb = tileb + buf * BT_C * LDR;
+    // The tile's A fragments are read from LDS two k-steps ahead of the MFMAs that use them (the
+    // scheduling barriers keep the compiler from serialising each read with its MFMAs), and the
+    // wave raises its issue priority while it feeds the matrix cores, so that the other wave on
+    // the SIMD runs its epilogue meanwhile.
+    __builtin_amdgcn_s_setprio(1);
+    bf16x8 a[3][2];
+#pragma unroll
+    for (int kk = 0; kk < 2; kk++)
+#pragma unroll
+      for (int cb = 0; cb < 2; cb++)
+        a[kk][cb] = __builtin_bit_cast(bf16x8, *(const uint4*)(tb + (cb * 32 + l32) * LDR + kk * 16 + half * 8));
 #pragma unroll
     for (int ks = 0; ks < KS; ks++) {
-      bf16x8 a[2];
+      if (ks + 2 < KS) {
 #pragma unroll
-      for (int cb = 0; cb < 2; cb++) {
-        const uint4 v = *(const uint4*)(tb + (cb * 32 + l32) * LDR + ks * 16 + half * 8);
-        a[cb] = __builtin_bit_cast(bf16x8, v);
+        for (int cb = 0; cb < 2; cb++)
+          a[(ks + 2) % 3][cb] =
+              __builtin_bit_cast(bf16x8, *(const uint4*)(tb + (cb * 32 + l32) * LDR + (ks + 2) * 16 + half * 8));
       }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int cb = 0; cb < 2; cb++)
 #pragma unroll
         for (int qb = 0; qb < NQB; qb++)
-          acc[cb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[cb], bq[qb][ks], acc[cb][qb], 0, 0, 0);
+          acc[cb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks % 3][cb], bq[qb][ks], acc[cb][qb], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
+    __builtin_amdgcn_s_setprio(0);
 
     // ---- epilogue: filter, then exact insertion for the rare hits
     if (t < ntiles) {
@@ -690,14 +704,14 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
     }  // t < ntiles
 
     if (NBUF == 2) {
-      KNN_COMMIT(s, buf ^ 1);
+      KNN_COMMIT(buf ^ 1);
       __syncthreads();
     } else {
       __syncthreads();            // every wave is done with the single buffer
-      KNN_COMMIT(s, 0);
+      KNN_COMMIT(0);
       __syncthreads();
     }
-    KNN_PREFETCH(s, KNN_TILE_AT(KNN_STEP_CLAMP(t + 3)));
+    KNN_PREFETCH(KNN_TILE_AT(KNN_STEP_CLAMP(t + 2)));
   };
   for (; t0 < ntiles; t0 += 2) {
     step(std::integral_constant<int, 0>{});

@@ -109,8 +109,17 @@ __global__ void gram_reduce_kernel(const double* __restrict__ part, int nblocks,
   if (active && *active == 0) return;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= 64 * 64) return;
+  // eight loads in flight ahead of the additions, which keep their order (bit-identical sums)
   double s = 0.0;
-  for (int b = 0; b < nblocks; b++) s += part[(int64_t)b * 64 * 64 + e];
+  int b = 0;
+  for (; b + 8 <= nblocks; b += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = part[(int64_t)(b + u) * 64 * 64 + e];
+#pragma unroll
+    for (int u = 0; u < 8; u++) s += v[u];
+  }
+  for (; b < nblocks; b++) s += part[(int64_t)b * 64 * 64 + e];
   G[e] = s;
 }
 

@@ -57,7 +57,7 @@ __global__ __launch_bounds__(TOPK_T) void topk_block_kernel(const int64_t* __res
 
 // single block: the k largest of all block candidates, then centre indices sorted ascending
 __global__ __launch_bounds__(TOPK_T) void topk_final_kernel(unsigned long long* __restrict__ cand, int64_t count, int k,
-                                                            int64_t n, int32_t* __restrict__ centres,
+                                                            int64_t /*n*/, int32_t* __restrict__ centres,
                                                             int32_t* __restrict__ centre_of) {
   __shared__ unsigned long long red[TOPK_T];
   __shared__ int32_t sel[64];

@@ -389,7 +389,7 @@ __global__ __launch_bounds__(256) void target_kernel(const TQ* __restrict__ Q, i
   __shared__ double Rs[64 * 64];
   __shared__ int cm[64];
   for (int e = threadIdx.x; e < k * k; e += 256) Rs[e] = R[e];
-  if (threadIdx.x < k) cm[threadIdx.x] = colmap[threadIdx.x];
+  if ((int)threadIdx.x < k) cm[threadIdx.x] = colmap[threadIdx.x];
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;

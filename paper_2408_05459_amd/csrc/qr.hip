@@ -357,7 +357,8 @@ template <typename T>
 ancka_status launch_apply(ancka_ctx* ctx, const T* Z, T* Q, int64_t n, int kp, int64_t ld, const double* Rinv,
                           const T* Qprev, double* dq_part, const int* active) {
   const unsigned grid = (unsigned)cdiv(n, 256);
-  const int kpm = kp <= 8 ? 8 : kp <= 16 ? 16 : kp <= 32 ? 32 : 64;
+  // the kernel computes every column below KPM (fully unrolled), so KPM follows kp closely
+  const int kpm = kp <= 8 ? 8 : kp <= 16 ? 16 : kp <= 32 ? 32 : kp <= 40 ? 40 : kp <= 48 ? 48 : kp <= 52 ? 52 : kp <= 56 ? 56 : 64;
   const int vw = 16 / (int)sizeof(T);
   const auto al16 = [](const void* p) { return p == nullptr || ((uintptr_t)p % 16) == 0; };
   const int vec = (ld % vw == 0 && ld >= kpm && al16(Z) && al16(Q) && al16(Qprev)) ? 1 : 0;
@@ -367,6 +368,14 @@ ancka_status launch_apply(ancka_ctx* ctx, const T* Z, T* Q, int64_t n, int kp, i
     apply_rinv_kernel<T, 16><<<grid, 256, 0, ctx->stream>>>(Z, Q, n, kp, ld, Rinv, Qprev, dq_part, active, vec);
   else if (kp <= 32)
     apply_rinv_kernel<T, 32><<<grid, 256, 0, ctx->stream>>>(Z, Q, n, kp, ld, Rinv, Qprev, dq_part, active, vec);
+  else if (kp <= 40)
+    apply_rinv_kernel<T, 40><<<grid, 256, 0, ctx->stream>>>(Z, Q, n, kp, ld, Rinv, Qprev, dq_part, active, vec);
+  else if (kp <= 48)
+    apply_rinv_kernel<T, 48><<<grid, 256, 0, ctx->stream>>>(Z, Q, n, kp, ld, Rinv, Qprev, dq_part, active, vec);
+  else if (kp <= 52)
+    apply_rinv_kernel<T, 52><<<grid, 256, 0, ctx->stream>>>(Z, Q, n, kp, ld, Rinv, Qprev, dq_part, active, vec);
+  else if (kp <= 56)
+    apply_rinv_kernel<T, 56><<<grid, 256, 0, ctx->stream>>>(Z, Q, n, kp, ld, Rinv, Qprev, dq_part, active, vec);
   else
     apply_rinv_kernel<T, 64><<<grid, 256, 0, ctx->stream>>>(Z, Q, n, kp, ld, Rinv, Qprev, dq_part, active, vec);
   LAUNCH_CHECK(ctx);

@@ -51,15 +51,10 @@ __global__ __launch_bounds__(256) void disc_pass_kernel(const T* __restrict__ Q,
                                                         unsigned int* __restrict__ cg,
                                                         const DiscState* __restrict__ st, double fscale) {
   if (st->done) return;
-  __shared__ __align__(16) T Rs[KM][KM];   // Rs[j][c] = R[c][j] (zero outside k x k)
   __shared__ unsigned long long Ss[KM * KM];   // Ss[c][label]: lanes of different labels hit different banks
   __shared__ unsigned int cs[KM];
   const int tid = threadIdx.x;
-  for (int e = tid; e < KM * KM; e += 256) {
-    const int j = e / KM, c = e % KM;
-    Rs[j][c] = (c < k && j < k) ? R[c * k + j] : (T)0;
-    Ss[e] = 0ull;
-  }
+  for (int e = tid; e < KM * KM; e += 256) Ss[e] = 0ull;
   if (tid < KM) cs[tid] = 0u;
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * 256 + tid;
@@ -112,12 +107,14 @@ __global__ __launch_bounds__(256) void disc_pass_kernel(const T* __restrict__ Q,
 #pragma unroll
         for (int c = 0; c < KM; c += VW) {
           if (c >= k) continue;   // R^T rows are zero beyond column k
+          // R^T row j from global memory at addresses every lane shares (scalar loads: a
+          // broadcast read of LDS would cost a full 64-lane transfer per 16 bytes)
           T r[VW];
           if constexpr (VW == 4) {
-            const float4 v = *(const float4*)&Rs[j][c];
+            const float4 v = *(const float4*)(R + j * KM + c);
             r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
           } else {
-            const double2 v = *(const double2*)&Rs[j][c];
+            const double2 v = *(const double2*)(R + j * KM + c);
             r[0] = v.x; r[1] = v.y;
           }
 #pragma unroll
@@ -389,7 +386,7 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
           const int a = e / k, b = e % k;
           t += X[a][b] * A[a][b];   // R[a][b] M[b][a]
           Rd[e] = X[a][b];
-          Rt[e] = (T)X[a][b];
+          Rt[b * KM + a] = (T)X[a][b];
         }
         ssum = block_sum4(t, red);
       }
@@ -488,7 +485,7 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
       double s = 0.0;
       for (int j = 0; j < k; j++) s += V[j][a] * A[j][b];
       Rd[e] = s;
-      Rt[e] = (T)s;
+      Rt[b * KM + a] = (T)s;
     }
   }
   if (tid == 0) {
@@ -501,15 +498,16 @@ __global__ __launch_bounds__(256) void disc_svd_kernel(unsigned long long* __res
 }
 
 template <typename T>
-__global__ void disc_init_kernel(int k, double* __restrict__ Rd, T* __restrict__ Rt, DiscState* __restrict__ st,
+__global__ void disc_init_kernel(int k, int km, double* __restrict__ Rd, T* __restrict__ Rt, DiscState* __restrict__ st,
                                  unsigned long long* __restrict__ Sg, unsigned int* __restrict__ cg) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < k * k) {
     const double v = (e / k == e % k) ? 1.0 : 0.0;
     Rd[e] = v;
-    Rt[e] = (T)v;
     Sg[e] = 0ull;
   }
+  // R^T with row stride km, zero outside k x k (the row pass reads whole 16-byte groups)
+  if (e < km * km) Rt[e] = (e / km == e % km && e / km < k) ? (T)1 : (T)0;
   if (e < k) cg[e] = 0u;
   if (e == 0) {
     st->done = 0;
@@ -552,7 +550,8 @@ ancka_status disc_launch(ancka_ctx* ctx, const T* Q, int64_t n, int k, int64_t l
   unsigned int* cg = b.cg;
   DiscState* st = b.st;
   const double fscale = fix_scale(n);
-  disc_init_kernel<T><<<16, 256, 0, ctx->stream>>>(k, Rd, Rt, st, Sg, cg);
+  static_assert(KM * KM <= 16 * 256, "disc_init_kernel covers R^T with 16 x 256 threads");
+  disc_init_kernel<T><<<16, 256, 0, ctx->stream>>>(k, KM, Rd, Rt, st, Sg, cg);
   LAUNCH_CHECK(ctx);
   const unsigned grid = (unsigned)cdiv(n, 256);
   // vector reads from Q - voff when that is 16-byte aligned (voff = 0 or 1 columns back)

@@ -263,14 +263,17 @@ __global__ __launch_bounds__(256) void apply_rinv_kernel(const T* __restrict__ Z
 #pragma unroll
     for (int j0 = 0; j0 < KPM; j0 += VW) {
       T qv[VW];
+      // the VW sums advance together over c (each keeps its own order c = 0 .. j)
+      double sv[VW];
 #pragma unroll
-      for (int u = 0; u < VW; u++) {
-        const int j = j0 + u;
-        double s = 0.0;
+      for (int u = 0; u < VW; u++) sv[u] = 0.0;
 #pragma unroll
-        for (int c = 0; c <= j; c++) s = fma(z[c], Rs(c, j), s);
-        qv[u] = (T)s;
-      }
+      for (int c = 0; c < j0 + VW; c++)
+#pragma unroll
+        for (int u = 0; u < VW; u++)
+          if (c <= j0 + u) sv[u] = fma(z[c], Rs(c, j0 + u), sv[u]);
+#pragma unroll
+      for (int u = 0; u < VW; u++) qv[u] = (T)sv[u];
       if (j0 < kp) {
         if (Qprev) {
           const VT pv = *(const VT*)(Qprev + r * ld + j0);

@@ -333,7 +333,7 @@ def main():
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm start comparison")
     ap.add_argument("--no-ivf", action="store_true", help="skip the IVF (approximate KNN) comparison")
     ap.add_argument("--ivf-nlist", type=int, default=1024)
-    ap.add_argument("--ivf-nprobe", type=int, default=16)
+    ap.add_argument("--ivf-nprobe", type=int, default=32)
     ap.add_argument("--ws-graphs", type=int, default=200)
     ap.add_argument("--ws-n", type=int, default=50000)
     ap.add_argument("--ws-epochs", type=int, default=8)

@@ -92,7 +92,7 @@ typedef struct {
   int32_t q_dtype;       /* ANCKA_F32 or ANCKA_F64: precision of the iterated block */
   int32_t early_stop;    /* 1: apply Eqs. (tcond-1) and (tcond-2); 0: run exactly T_a iterations */
   int32_t ivf_nlist;     /* knn_mode IVF_BF16: lists of the coarse quantiser (default 1024) */
-  int32_t ivf_nprobe;    /* knn_mode IVF_BF16: lists each query block scans (default 16) */
+  int32_t ivf_nprobe;    /* knn_mode IVF_BF16: lists each query block scans (default 32) */
 } ancka_params;
 
 typedef struct {

@@ -129,7 +129,7 @@ ancka_params ancka_default_params(void) {
   p.q_dtype = ANCKA_F32;
   p.early_stop = 1;
   p.ivf_nlist = 1024;
-  p.ivf_nprobe = 16;
+  p.ivf_nprobe = 32;
   return p;
 }
 

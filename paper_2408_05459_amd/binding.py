@@ -126,6 +126,11 @@ class Lib:
         if not os.path.exists(path):
             raise RuntimeError(f"libancka.so not found at {path}: build it with `python -m paper_2408_05459_amd.build`")
         self.path = path
+        # torch first: its HIP runtime then serves this library too (the library's own reference
+        # to the runtime resolves to the copy already loaded), so streams and device memory
+        # handed over by torch belong to the runtime the library calls.  Loaded the other way
+        # round, the process ends up with two runtimes and context creation fails.
+        import torch  # noqa: F401
         self.cdll = C.CDLL(path)
         for name, (res, args) in _SIGS.items():
             f = getattr(self.cdll, name)

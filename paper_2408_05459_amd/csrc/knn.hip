@@ -231,7 +231,7 @@ constexpr int NPIV = 64;   // coarse cells of the scan order
 // slots hold (+inf, -1) and are never the worst), in LDS or in global memory.  The caller keeps
 // the list's worst entry (score ws, index wj, slot wp) under the order (score desc, index asc) in
 // registers.  list_worst finds it with 16-byte reads, eight entries per step; list_replace_worst
-// puts (s, jj) in its place and finds the new worst.  The list ends as the top entries of that
+// puts (s, jj) in its place and returns the new worst.  The list ends as the top entries of that
 // total order whatever order candidates arrive in.
 __device__ __forceinline__ void list_worst(const float* ls, const int* li, int kpp, float& ws, int& wj, int& wp) {
   float bs = INFINITY;
@@ -259,11 +259,24 @@ __device__ __forceinline__ void list_worst(const float* ls, const int* li, int k
   wp = bp;
 }
 
-__device__ __forceinline__ void list_replace_worst(float* ls, int* li, int kpp, float s, int jj, float& ws, int& wj,
-                                                   int& wp) {
-  ls[wp] = s;
-  li[wp] = jj;
-  list_worst(ls, li, kpp, ws, wj, wp);
+// Empty slots (-inf, INT_MAX) are the worst entries there are, and list_worst returns the first
+// of equal worst entries, so a list fills its slots in order: the empty slots are always a
+// suffix.  Filling an empty slot then leaves the next slot as the new worst when that one is
+// empty too, and no scan is needed.  Kept out of line: the insertion runs at 32 places of each
+// epilogue, and inlined copies crowd the kernel's registers.
+struct ListWorst {
+  float s;
+  int j;
+  int p;
+};
+__device__ __noinline__ ListWorst list_replace_worst(float* ls, int* li, int kpp, float s, int jj, ListWorst w) {
+  const bool was_empty = w.j == INT_MAX;
+  ls[w.p] = s;
+  li[w.p] = jj;
+  if (was_empty && w.p + 1 < kpp && li[w.p + 1] == INT_MAX) return ListWorst{-INFINITY, INT_MAX, w.p + 1};
+  ListWorst r;
+  list_worst(ls, li, kpp, r.s, r.j, r.p);
+  return r;
 }
 
 // Arguments of both passes.  Lists are kept per sorted row p in [0, npad): KPP slots (KP rounded
@@ -621,8 +634,12 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
                       const int jp = tperm[cl];
                       const float sc = a * iv;
                       // below the bound tq no candidate can end in the list
-                      if (iv > 0.0f && jp != qi && sc >= tq[qb] && better<float>(sc, jp, tcur, tcur_i))
-                        list_replace_worst(ls, li, KPP, sc, jp, tcur, tcur_i, wslot);
+                      if (iv > 0.0f && jp != qi && sc >= tq[qb] && better<float>(sc, jp, tcur, tcur_i)) {
+                        const ListWorst nw = list_replace_worst(ls, li, KPP, sc, jp, ListWorst{tcur, tcur_i, wslot});
+                        tcur = nw.s;
+                        tcur_i = nw.j;
+                        wslot = nw.p;
+                      }
                     }
                   }
                 }
@@ -819,7 +836,12 @@ __global__ __launch_bounds__(256) void knn_merge_kernel(int64_t n, int KP, int R
       const uint64_t v = hval[e];
       const float s = __uint_as_float((uint32_t)(v & 0xffffffffu));
       const int j = (int)(v >> 32);
-      if (better<float>(s, j, ws, wj)) list_replace_worst(ls, li, KPP, s, j, ws, wj, wp);
+      if (better<float>(s, j, ws, wj)) {
+        const ListWorst nw = list_replace_worst(ls, li, KPP, s, j, ListWorst{ws, wj, wp});
+        ws = nw.s;
+        wj = nw.j;
+        wp = nw.p;
+      }
     }
   }
   // (slots KP.. hold (+inf, -1) and are never replaced: the list is the first KP slots)

@@ -223,7 +223,8 @@ __global__ __launch_bounds__(256) void knn_vector_kernel(const TX* __restrict__ 
 // query's sorted list in LDS; the two half-waves, which hold different candidates of the same
 // queries, insert one after the other.
 constexpr int BT_C = 64;   // candidates per tile
-constexpr int TAU_T = 11;  // bound pass: values kept per lane (lists up to 2 TAU_T - 1 = 21 long)
+constexpr int TAU_T = 11;   // bound pass: values kept per lane (lists up to 2 TAU_T - 1 = 21 long)
+constexpr int TAU_T2 = 21;  // the bound pass for lists of 22 .. 41 entries
 enum { SCAN_WIN = 0, SCAN_SYM = 1, SCAN_TAU = 2 };
 constexpr int NPIV = 64;   // coarse cells of the scan order
 
@@ -315,7 +316,7 @@ struct ScanArgs {
 
 // LG: the lists stay in global memory (args.lsim / args.lidx) instead of LDS, for list lengths
 // whose LDS copy would leave room for fewer than two workgroups per CU.
-template <int DP, int QW, int NBUF, int MODE, bool LG>
+template <int DP, int QW, int NBUF, int MODE, bool LG, int TT = TAU_T>
 __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(ScanArgs args) {
   constexpr bool SYM = MODE == SCAN_SYM;
   constexpr bool TAU = MODE == SCAN_TAU;
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
   float thr[NQB];
   float tq[NQB];     // window pass: the bound pass's lower bound, a floor for the threshold
   float colq[NQB];   // symmetric pass: 1/|x_i| of the lane's query (0: the query takes no part)
-  float rt[NQB][TAU_T];  // bound pass: the lane's TAU_T largest bound scores, descending
+  float rt[NQB][TT];  // bound pass: the lane's TT largest bound scores, descending
   float wv[NQB];     // worst entry of the query's list: score, index, slot (both halves hold it)
   int wi[NQB], wp[NQB];
   int qloc[NQB];
@@ -401,7 +402,7 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
     thr[qb] = iq > 0.0f ? (SYM ? wv[qb] : tq[qb]) : INFINITY;
     colq[qb] = iq;
 #pragma unroll
-    for (int j = 0; j < TAU_T; j++) rt[qb][j] = -INFINITY;
+    for (int j = 0; j < TT; j++) rt[qb][j] = -INFINITY;
 #pragma unroll
     for (int ks = 0; ks < KS; ks++) {
       const uint4 v = *(const uint4*)(args.Xs + qs * DP + ks * 16 + half * 8);
@@ -570,25 +571,25 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
 #pragma unroll
         for (int i = 0; i < 16; i++) m = fmaxf(m, acc[cb][qb][i]);
       if (TAU) {
-        // the lane keeps the TAU_T largest list scores a / |x_j| (a > 0) it sees; a * c, c the
+        // the lane keeps the TT largest list scores a / |x_j| (a > 0) it sees; a * c, c the
         // tile's smallest 1/|x_j|, is no larger (rounding is monotone) and screens candidates
         // before 1/|x_j| is read
         const float c = tmn[2 + buf];
-        if (__ballot(m * c > rt[qb][TAU_T - 1])) {
+        if (__ballot(m * c > rt[qb][TT - 1])) {
 #pragma unroll
           for (int cb = 0; cb < 2; cb++)
 #pragma unroll
             for (int g = 0; g < 4; g++) {
               const float g4 = fmaxf(fmaxf(acc[cb][qb][4 * g], acc[cb][qb][4 * g + 1]),
                                      fmaxf(acc[cb][qb][4 * g + 2], acc[cb][qb][4 * g + 3]));
-              if (g4 * c > rt[qb][TAU_T - 1]) {
+              if (g4 * c > rt[qb][TT - 1]) {
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                   const float av = acc[cb][qb][4 * g + r];
                   float x = av * tinv[buf * BT_C + cb * 32 + 8 * g + 4 * half + r];
-                  if (av > 0.0f && av * c > rt[qb][TAU_T - 1] && x > rt[qb][TAU_T - 1]) {
+                  if (av > 0.0f && av * c > rt[qb][TT - 1] && x > rt[qb][TT - 1]) {
 #pragma unroll
-                    for (int j = 0; j < TAU_T; j++) {
+                    for (int j = 0; j < TT; j++) {
                       const float hi = fmaxf(rt[qb][j], x);
                       x = fminf(rt[qb][j], x);
                       rt[qb][j] = hi;
@@ -736,17 +737,17 @@ __global__ __launch_bounds__(256, (DP <= 128 ? 2 : 1)) void knn_bf16_kernel(Scan
   }
 
   if (TAU) {
-    // The two halves of a lane pair hold disjoint candidates of one query, so their 2 TAU_T
-    // values belong to 2 TAU_T distinct candidates (at most one of them the query itself), each
-    // with a list score at least the smaller of the two TAU_T-th values.  With 2 TAU_T - 1 >= KP
+    // The two halves of a lane pair hold disjoint candidates of one query, so their 2 TT
+    // values belong to 2 TT distinct candidates (at most one of them the query itself), each
+    // with a list score at least the smaller of the two TT-th values.  With 2 TT - 1 >= KP
     // that value is a lower bound of the query's KP-th best list score; -inf when a half saw
-    // fewer than TAU_T positive scores, or when KP is too long for TAU_T.
+    // fewer than TT positive scores, or when KP is too long for TT.
 #pragma unroll
     for (int qb = 0; qb < NQB; qb++) {
-      const float own = rt[qb][TAU_T - 1];
+      const float own = rt[qb][TT - 1];
       const float other = __shfl_xor(own, 32, ANCKA_WAVE);
       const float t = fminf(own, other);
-      if (half == 0) args.tau[q0 + qloc[qb]] = (2 * TAU_T - 1 >= KP && t > 0.0f) ? t : -INFINITY;
+      if (half == 0) args.tau[q0 + qloc[qb]] = (2 * TT - 1 >= KP && t > 0.0f) ? t : -INFINITY;
     }
     return;
   }
@@ -1466,13 +1467,13 @@ constexpr int bf16_qb() {
 }
 int bf16_qw(int DP) { return DP <= 256 ? 64 : 32; }
 
-template <int DP, int QW, int NBUF, int MODE, bool LG>
+template <int DP, int QW, int NBUF, int MODE, bool LG, int TT = TAU_T>
 ancka_status launch_bf16(ancka_ctx* ctx, const ScanArgs& args, size_t sm) {
   // the LDS limit is a per-device attribute of the function: set it on every call (cheap), so a
   // context on another device sees it too
-  HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_bf16_kernel<DP, QW, NBUF, MODE, LG>,
+  HIP_TRY(ctx, hipFuncSetAttribute((const void*)knn_bf16_kernel<DP, QW, NBUF, MODE, LG, TT>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-  knn_bf16_kernel<DP, QW, NBUF, MODE, LG><<<(unsigned)args.nwg, 256, sm, ctx->stream>>>(args);
+  knn_bf16_kernel<DP, QW, NBUF, MODE, LG, TT><<<(unsigned)args.nwg, 256, sm, ctx->stream>>>(args);
   LAUNCH_CHECK(ctx);
   return ANCKA_OK;
 }
@@ -1487,7 +1488,9 @@ ancka_status run_bf16_t(ancka_ctx* ctx, const ScanArgs& args) {
   // one) still fit; longer lists are kept in global memory
   const size_t budget = (size_t)160 * 1024 / (DP <= 128 ? 2 : 1);
   if constexpr (MODE == SCAN_TAU) {
-    return launch_bf16<DP, QW, NBUF, MODE, false>(ctx, args, base);
+    // 2 TT - 1 values bound the list's last entry: 11 per lane up to 21 entries, else 21
+    if (args.KP <= 2 * TAU_T - 1) return launch_bf16<DP, QW, NBUF, MODE, false, TAU_T>(ctx, args, base);
+    return launch_bf16<DP, QW, NBUF, MODE, false, TAU_T2>(ctx, args, base);
   } else {
     if (base + lists <= budget) return launch_bf16<DP, QW, NBUF, MODE, false>(ctx, args, base + lists);
     return launch_bf16<DP, QW, NBUF, MODE, true>(ctx, args, base);
@@ -1791,7 +1794,7 @@ ancka_status knn_typed(ancka_ctx* ctx, const TX* X, int64_t n, int64_t d, int64_
         ST_TRY(ws_get_t(ctx, "knn_tthr", (size_t)nt, &tthr));
         sa.tile_thr = tthr;
         sa.tile_cinv = tcinv;
-        if (2 * TAU_T - 1 >= KP) ST_TRY(ws_get_t(ctx, "knn_tau", (size_t)npad, &sa.tau));
+        if (2 * TAU_T2 - 1 >= KP) ST_TRY(ws_get_t(ctx, "knn_tau", (size_t)npad, &sa.tau));
         sa.hcap = handover_capacity(n);
         ST_TRY(ws_get_t(ctx, "knn_hkey", (size_t)sa.hcap, &sa.hkey));
         ST_TRY(ws_get_t(ctx, "knn_hval", (size_t)sa.hcap, &sa.hval));
@@ -1978,7 +1981,7 @@ ancka_status ivf_knn(ancka_ctx* ctx, const uint16_t* X, int64_t n, int64_t d, in
   ST_TRY(ws_get_t(ctx, "knn_lidx", (size_t)npad * KPP, &sa.lidx));
   ST_TRY(ws_get_t(ctx, "knn_lsim", (size_t)npad * KPP, &sa.lsim));
   ST_TRY(ws_get_t(ctx, "knn_colthr", (size_t)npad, &sa.colthr));
-  if (2 * TAU_T - 1 >= KP) ST_TRY(ws_get_t(ctx, "knn_tau", (size_t)npad, &sa.tau));
+  if (2 * TAU_T2 - 1 >= KP) ST_TRY(ws_get_t(ctx, "knn_tau", (size_t)npad, &sa.tau));
   int32_t* cidx = nullptr;
   float* csim = nullptr;
   ST_TRY(ws_get_t(ctx, "knn_cidx", (size_t)n * KP, &cidx));

@@ -97,9 +97,10 @@ def test_default_window_uses_symmetric_pass(lib, monkeypatch):
     assert check_knn_rows(X.astype(np.float32), rows, gi[rows], gs[rows], 10, 2 * gamma_d(128, 2.0 ** -24)) <= 1
 
 
-@pytest.mark.parametrize("K", [10, 11, 16])
+@pytest.mark.parametrize("K", [10, 11, 16, 20, 21])
 def test_list_lengths_around_the_bound_pass(lib, monkeypatch, K):
-    # 2K <= 21: the window pass starts from the bound pass's lower bounds; longer lists skip it
+    # the window pass starts from the bound pass's lower bounds: 11 values per lane bound lists up
+    # to 2K = 21, 21 values lists up to 41; longer lists (K = 21) skip the bound pass
     n = 9000
     X = data(n, 21 + K)
     gi_w, gs_w, st_w = run(lib, X, K, monkeypatch, window=2)

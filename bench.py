@@ -450,6 +450,7 @@ def main():
     spmm_ms = e0.elapsed_time(e1) / a.spmm_reps
     spmm_bytes = spmm_compulsory_bytes(oinfo, n, net.L, kp)
     spmm_gbps = spmm_bytes / (spmm_ms * 1e-3) / 1e9
+    spmm_traffic = committed_traffic("spmm_kernel")
     # the same product with Q stored in BF16 (measured beside; the method keeps FP32 blocks)
     Qb = Q.to(torch.bfloat16)
     for _ in range(3):
@@ -544,7 +545,9 @@ def main():
                 "mfma_counters": {p: committed_mfma(p) for p in ("bound", "window", "symmetric")},
                 "rescanned": last["knn_rescanned"]},
         "spmm": {"ms": round(spmm_ms, 3), "compulsory_bytes": spmm_bytes, "gbps_compulsory": round(spmm_gbps, 1),
-                 "traffic_bytes": committed_traffic("spmm_kernel"),
+                 "traffic_bytes": spmm_traffic,
+                 # counter bytes read and written beyond L2 per launch over this run's launch time
+                 "gbps_traffic": (round(spmm_traffic / (spmm_ms * 1e-3) / 1e9, 1) if spmm_traffic else None),
                  "frac": round(spmm_gbps / PEAK_HBM_GBPS, 4),
                  "bf16_block": {"ms": round(spmm_bf16_ms, 3), "compulsory_bytes": spmm_bf16_bytes,
                                 "gbps_compulsory": round(spmm_bf16_bytes / (spmm_bf16_ms * 1e-3) / 1e9, 1)},
